@@ -1,0 +1,181 @@
+"""Anelastic wave equations: Jacobians, coupling and the Riemann solver (test
+infrastructure: CPU oracle).
+
+Sec. II (eq. hyp_sys): q_t + A q_x + B q_y + C q_z = E q with
+q = (sigma_xx, sigma_yy, sigma_zz, sigma_xy, sigma_yz, sigma_xz, u, v, w,
+     theta^1_xx .. theta^1_xz, ..., theta^m_xx .. theta^m_xz).
+The paper names u, v and "v" for the velocities; the third is read as w.
+The Jacobians carry an elastic 9x9 block and an anelastic 6x9 block that only
+touches the velocities; E couples the memory variables into the stresses and
+relaxes them (its diagonal part E').  The paper delegates the entries to its
+references; this oracle writes out the standard velocity-stress system:
+
+  d/dt sigma      = lambda tr(eps') I + 2 mu eps'
+                    - sum_l [a_l tr(theta^l) I + b_l theta^l]
+  rho d/dt v      = div sigma
+  d/dt theta^l    = omega_l (eps' - theta^l)        eps' = sym grad v
+
+with a_l = (lambda + 2 mu) Y^P_l - 2 mu Y^S_l (= lambda Y^lambda_l) and
+b_l = 2 mu Y^S_l.  lambda, mu are the unrelaxed moduli from (rho, vp, vs).
+The relaxation sign is the decaying one (-omega_l); the time-kernel equation of
+Sec. II-A prints +omega_l, the volume kernel -omega_l, and only the latter is
+stable.
+
+Riemann solver (the paper gives none): Godunov.  For a face with unit normal n
+pointing from the element (-) to its neighbour (+), the interface state keeps
+each side's outgoing characteristics and makes traction sigma n and velocity
+continuous.  It is built here from eigenvectors: q*- = q- + R- alpha with R-
+the eigenvectors of A_n^- with negative speeds, q*+ = q+ + R+ beta with R+ those
+of A_n^+ with positive speeds, and the 6x6 continuity system solved for
+(alpha, beta).  The flux seen by the element is A_n^- q*-.
+Free surface: traction of q* is zero.  Absorbing: the incoming characteristic
+amplitudes of q- are removed (projector built from left eigenvectors).
+
+Pins (tests/test_oracle_physics.py): eigenvalues {+-vp, +-vs x2, 0 x3}; the
+homogeneous flux equals 1/2 A_n (q- + q+) + 1/2 |A_n| (q- - q+) with
+|A_n| = R |Lambda| R^-1; normal-incidence reflection (Z2-Z1)/(Z2+Z1); zero
+traction at the free surface; absorbing flux equals the Godunov flux against a
+zero ghost state.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SYM = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+SYM_INDEX = {}
+for _q, (_i, _j) in enumerate(SYM):
+    SYM_INDEX[(_i, _j)] = _q
+    SYM_INDEX[(_j, _i)] = _q
+VEL = 6
+
+
+def n_quantities(m: int) -> int:
+    return 9 + 6 * m
+
+
+def lame(rho, vp, vs):
+    rho, vp, vs = (np.asarray(a, dtype=np.float64) for a in (rho, vp, vs))
+    mu = rho * vs * vs
+    lam = rho * vp * vp - 2.0 * mu
+    return lam, mu
+
+
+def jacobians(rho, lam, mu, omega):
+    """A[K, 3, Nq, Nq]: Jacobians in x, y, z per element."""
+    K = len(rho)
+    m = len(omega)
+    nq = n_quantities(m)
+    A = np.zeros((K, 3, nq, nq))
+    for d in range(3):
+        for q, (i, j) in enumerate(SYM):
+            for k in range(3):
+                c = lam * (i == j) * (d == k) + mu * ((i == d) * (j == k) + (j == d) * (i == k))
+                A[:, d, q, VEL + k] = -c
+                for l in range(m):
+                    A[:, d, 9 + 6 * l + q, VEL + k] = -omega[l] * 0.5 * ((i == d) * (j == k) + (j == d) * (i == k))
+        for i in range(3):
+            A[:, d, VEL + i, SYM_INDEX[(i, d)]] = -1.0 / rho
+    return A
+
+
+def coupling(lam, mu, yp, ys, omega):
+    """E[K, Nq, Nq]: anelastic source matrix (zero for m = 0)."""
+    K = len(lam)
+    m = len(omega)
+    nq = n_quantities(m)
+    E = np.zeros((K, nq, nq))
+    for l in range(m):
+        a = (lam + 2.0 * mu) * yp[:, l] - 2.0 * mu * ys[:, l]
+        b = 2.0 * mu * ys[:, l]
+        base = 9 + 6 * l
+        for q in range(6):
+            E[:, q, base + q] -= b
+            if q < 3:
+                for r in range(3):
+                    E[:, q, base + r] -= a
+            E[:, base + q, base + q] = -omega[l]
+    return E
+
+
+def normal_jacobian(A, n):
+    """A_n = sum_d n_d A_d for A[F,3,nq,nq], n[F,3]."""
+    return np.einsum("fd,fdij->fij", n, A)
+
+
+def traction_op(n):
+    """Tr[F,3,9]: traction sigma n as a linear map of the elastic state."""
+    F = n.shape[0]
+    T = np.zeros((F, 3, 9))
+    for i in range(3):
+        for j in range(3):
+            T[:, i, SYM_INDEX[(i, j)]] += n[:, j]
+    return T
+
+
+def velocity_op(F):
+    V = np.zeros((F, 3, 9))
+    for i in range(3):
+        V[:, i, VEL + i] = 1.0
+    return V
+
+
+def _sorted_eig(M):
+    """Real eigen-decomposition of matrices with real spectra, sorted by speed.
+    LAPACK may return a complex-conjugate pair of eigenvectors for a repeated
+    real eigenvalue (round-off imaginary parts); such a pair is replaced by the
+    real and imaginary parts of its first member, which span the same real
+    eigenspace."""
+    w, R = np.linalg.eig(M)
+    Rr = R.real.copy()
+    for j in range(M.shape[1] - 1):
+        pair = w.imag[:, j] > 0
+        if np.any(pair):
+            Rr[pair, :, j] = R[pair, :, j].real
+            Rr[pair, :, j + 1] = R[pair, :, j].imag
+    w = w.real
+    order = np.argsort(w, axis=1, kind="stable")
+    w = np.take_along_axis(w, order, axis=1)
+    Rr = np.take_along_axis(Rr, order[:, None, :], axis=2)
+    return w, Rr
+
+
+def godunov_matrices(An_m, An_p, n, kind):
+    """Interface-state maps: q*- = Gm q- + Gp q+ (elastic 9 components).
+
+    An_m, An_p: [F,9,9] elastic normal Jacobians of the element and of its
+    neighbour; kind [F]: 0 interior, 1 free surface, 2 absorbing."""
+    F = An_m.shape[0]
+    I9 = np.broadcast_to(np.eye(9), (F, 9, 9))
+    wm, Rm = _sorted_eig(An_m)
+    wp, Rp = _sorted_eig(An_p)
+    Rin = Rm[:, :, :3]     # three most negative speeds: waves leaving the face into (-)
+    Rout = Rp[:, :, 6:]    # three most positive speeds: waves leaving into (+)
+    Tr = traction_op(n)
+    Vl = velocity_op(F)
+    Gm = np.zeros((F, 9, 9))
+    Gp = np.zeros((F, 9, 9))
+
+    inner = kind == 0
+    if np.any(inner):
+        M = np.zeros((F, 6, 6))
+        M[:, :3, :3] = Tr @ Rin
+        M[:, :3, 3:] = -(Tr @ Rout)
+        M[:, 3:, :3] = Vl @ Rin
+        M[:, 3:, 3:] = -(Vl @ Rout)
+        rhs = np.concatenate([Tr, Vl], axis=1)          # applied to (q+ - q-)
+        sol = np.linalg.solve(M[inner], rhs[inner])     # [f,6,9]
+        S_alpha = sol[:, :3, :]
+        Gp[inner] = Rin[inner] @ S_alpha
+        Gm[inner] = I9[inner] - Gp[inner]
+    free = kind == 1
+    if np.any(free):
+        TR = Tr[free] @ Rin[free]
+        Gm[free] = I9[free] - Rin[free] @ np.linalg.solve(TR, Tr[free])
+    absorb = kind == 2
+    if np.any(absorb):
+        wl, Lt = _sorted_eig(np.transpose(An_m[absorb], (0, 2, 1)))  # left eigenvectors
+        Lin = Lt[:, :, :3]
+        P = np.transpose(Lin, (0, 2, 1)) @ Rin[absorb]                 # [f,3,3]
+        proj = Rin[absorb] @ np.linalg.solve(P, np.transpose(Lin, (0, 2, 1)))
+        Gm[absorb] = I9[absorb] - proj
+    return Gm, Gp
