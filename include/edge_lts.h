@@ -1,0 +1,182 @@
+/*
+ * edge_lts.h -- C-ABI of the MI355X (gfx950) ADER-DG solver for the elastic
+ * and anelastic wave equations on unstructured tetrahedral meshes, with
+ * clustered rate-2 local time stepping.
+ *
+ * The operations follow Breuer & Heinecke, "Next-Generation Local Time
+ * Stepping for the ADER-DG Finite Element Method" (arXiv 2202.10313):
+ *   - the PDE and state vector: Sec. II, eq. hyp_sys (q = 6 stresses,
+ *     3 velocities, 6m memory variables);
+ *   - the element update: Sec. II-A (time kernel eq. ader_taylor with the
+ *     Cauchy-Kowalevski recursion, volume and surface kernels, eq. update);
+ *   - clusters and lambda: Sec. IV-A (interval definition of C_1..C_Nc,
+ *     normalisation, lambda search in steps of 0.01);
+ *   - buffers and schedule: Sec. IV-B (eq. lts_buffers and the walk-through
+ *     of Fig. lts_scheme).
+ * Point sources, receivers, boundary conditions and the Riemann solver are not
+ * specified by the paper; the choices made are documented per function.
+ *
+ * Conventions shared by every call:
+ *   - return value 0 on success, a negative EDG_E* code on failure; the
+ *     message of the last failure is available from edg_last_error(ctx);
+ *     no call aborts the process or throws across the ABI;
+ *   - every array argument is a host pointer owned by the caller and is only
+ *     read (or written, for outputs) during the call; the library copies
+ *     what it keeps;
+ *   - element data is in the caller's element order and the caller's local
+ *     vertex order; internally elements are reordered by cluster and each
+ *     tet's vertices are sorted by vertex id, which the library undoes on
+ *     every read;
+ *   - floating-point inputs and outputs are FP64; the internal arithmetic is
+ *     FP32 or FP64 as configured;
+ *   - modal coefficients use the orthonormal Dubiner basis on the unit
+ *     tetrahedron (0,0,0),(1,0,0),(0,1,0),(0,0,1) of the tet's own vertex
+ *     order, ordered by total degree, then i, then j descending; quantity
+ *     order sxx,syy,szz,sxy,syz,sxz,u,v,w, then the memory variables of each
+ *     mechanism in the same stress-component order.
+ */
+#ifndef EDGE_LTS_H
+#define EDGE_LTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EDG_OK 0
+#define EDG_EINVAL -1    /* bad argument (size, range, null where required) */
+#define EDG_ESTATE -2    /* call out of order (e.g. advance before clusters) */
+#define EDG_ENOMEM -3    /* device or host allocation failed */
+#define EDG_EHIP -4      /* a HIP runtime call failed */
+#define EDG_ENOTSYNC -5  /* time is not a synchronisation point */
+#define EDG_EMESH -6     /* non-conforming mesh, degenerate tet, unmatched face */
+#define EDG_ECAP -7      /* output capacity too small */
+
+#define EDG_BC_INTERIOR 0
+#define EDG_BC_FREE 1     /* free surface: zero traction (mirror state) */
+#define EDG_BC_ABSORB 2   /* absorbing: no incoming characteristics (zero state) */
+
+#define EDG_STF_RICKER 0  /* moment rate (1-2a(t-t0)^2) exp(-a(t-t0)^2), a=(pi fc)^2; params [fc, t0] */
+#define EDG_STF_HANN 1    /* moment rate (1-cos(2 pi (t-t0)/T))/T on [t0,t0+T]; params [t0, T] */
+
+typedef struct edg_ctx edg_ctx;
+
+typedef struct {
+  int32_t order;       /* O in 2..5 (B(O) = O(O+1)(O+2)/6 basis functions) */
+  int32_t mechanisms;  /* relaxation mechanisms m: 0 (elastic) or 3 */
+  int32_t n_runs;      /* independent runs sharing the mesh: 1 */
+  int32_t n_clusters;  /* N_c in 1..5 */
+  int32_t fp64;        /* 1: FP64 state and arithmetic, 0: FP32 */
+  double cfl;          /* C in dt_k = C 2 r_k / ((2(O-1)+1) vp_k), r_k the insphere radius */
+  double lambda;       /* lambda in (0.5, 1]; <= 0 searches 0.51..1.00 (max speedup, ties -> larger) */
+  void* hip_stream;    /* hipStream_t the library launches on (NULL: its own stream) */
+  int32_t device;      /* HIP device ordinal */
+  uint32_t flags;      /* reserved, 0 */
+} edg_config;
+
+/* Create a context on cfg->device.  *out receives the handle (NULL on
+ * failure; creation errors are returned only as codes). */
+int edg_create(const edg_config* cfg, edg_ctx** out);
+
+/* Mesh (Sec. II-A: conforming unstructured tetrahedra).  tet_verts [K][4]:
+ * vertex ids, used only to match faces (three shared ids = a shared face;
+ * periodic meshes reuse ids across the period); tet_xyz [K][4][3]: the tet's
+ * vertex coordinates in the same local order; face_bc [K][4]: EDG_BC_* per
+ * local face i (the face opposite local vertex i), NULL = all interior.
+ * EDG_EMESH if a face is shared by more than two tets, an unmatched face is
+ * tagged interior, a matched face carries a boundary tag, a tet repeats a
+ * vertex id or is degenerate. */
+int edg_upload_mesh(edg_ctx* ctx, int64_t n_tets, const int64_t* tet_verts, const double* tet_xyz,
+                    const int8_t* face_bc);
+
+/* Materials per element: density rho [kg/m^3], unrelaxed P and S speeds vp,
+ * vs [m/s] (vs > 0); for m > 0, the relaxation frequencies omega [m] (rad/s,
+ * shared by all elements) and the P/S weights yp, ys [K][m] of the
+ * generalised Maxwell body (stress relaxes by -sum_l (a_l tr(theta^l) I +
+ * b_l theta^l), a_l = (lambda+2mu) Yp_l - 2mu Ys_l, b_l = 2mu Ys_l; the memory
+ * variables obey d/dt theta^l = omega_l (sym grad v - theta^l)). */
+int edg_upload_materials(edg_ctx* ctx, const double* rho, const double* vp, const double* vs,
+                         const double* omega, const double* yp, const double* ys);
+
+/* Time clusters (Sec. IV-A).  cluster: [K] values 1..N_c in the caller's
+ * element order (used as given; EDG_EINVAL if two face neighbours differ by
+ * more than one), or NULL to derive them from the CFL steps, the interval
+ * rule, normalisation and the lambda of the configuration.  Allocates the
+ * device state; the DOFs start at zero and the time at 0. */
+int edg_upload_clusters(edg_ctx* ctx, const int32_t* cluster);
+
+/* Derived clustering: cluster_out [K] (may be NULL), dt_min (smallest CFL
+ * step), lambda, sync_dt (step of the coarsest cluster: the times
+ * edg_advance_to accepts are its multiples) and the theoretical speedup over
+ * global time stepping K / sum_l n_l / (2^(l-1) lambda).  Any pointer may be NULL. */
+int edg_get_clusters(const edg_ctx* ctx, int32_t* cluster_out, double* dt_min, double* lambda,
+                     double* sync_dt, double* speedup);
+
+/* Modal DOFs [K][Nq][B] of run `run` (0) at the current time.  Only at a
+ * synchronisation point (always true between calls). */
+int edg_set_initial(edg_ctx* ctx, int32_t run, const double* dofs);
+
+/* Moment-tensor point sources of run `run`: xyz [n][3], moment [n][6]
+ * (xx,yy,zz,xy,yz,xz, N m), stf_params [n][2] (see EDG_STF_*).  Each source
+ * adds -M phi(x_s)/|det J| times the exact integral of its moment rate over
+ * each step of the element that contains it (lowest element index on ties);
+ * EDG_EINVAL if a point is outside the mesh.  Replaces earlier sources. */
+int edg_set_sources(edg_ctx* ctx, int32_t run, int64_t n, const double* xyz, const double* moment,
+                    int32_t stf_kind, const double* stf_params);
+
+/* Receivers at xyz [n][3] sampling the 9 elastic quantities every dt_sample
+ * from t = 0 (n_samples samples); each sample comes from the Taylor
+ * expansion of the covering element's prediction for the step that contains
+ * the sample time.  Clears recorded samples. */
+int edg_set_receivers(edg_ctx* ctx, int64_t n, const double* xyz, double dt_sample, int64_t n_samples);
+
+/* Advance every element to time t (a multiple of sync_dt, not earlier than
+ * the current time; EDG_ENOTSYNC otherwise).  Runs on the context's stream
+ * and returns after the work has been enqueued and completed. */
+int edg_advance_to(edg_ctx* ctx, double t);
+
+/* Recorded seismograms of run `run`: out [n_rec][n_samples][9]; cap = number
+ * of doubles available (EDG_ECAP if smaller). */
+int edg_read_receivers(edg_ctx* ctx, int32_t run, double* out, int64_t cap);
+
+/* DOFs [K][Nq][B] of run `run` at the current time; cap = doubles available. */
+int edg_read_dofs(edg_ctx* ctx, int32_t run, double* out, int64_t cap);
+
+/* Current simulation time (0 for a NULL context). */
+double edg_time(const edg_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none; a static string for NULL). */
+const char* edg_last_error(const edg_ctx* ctx);
+
+/* Per-launch timing of the element-update kernel (HIP events on the
+ * context's stream): enable != 0 starts recording; edg_kernel_stats returns
+ * the number of timed launches, their total time [ms] and the number of
+ * element updates they performed.  Timing adds a synchronisation per launch. */
+int edg_enable_timing(edg_ctx* ctx, int32_t enable);
+int edg_kernel_stats(const edg_ctx* ctx, int64_t* launches, double* total_ms, int64_t* element_updates);
+
+/* Element updates (element x own step) performed so far. */
+int64_t edg_element_updates(const edg_ctx* ctx);
+
+/* Destroy the context and free its device memory (NULL is ignored). */
+void edg_destroy(edg_ctx* ctx);
+
+/* ---- host-only helpers (no device work; for tests and tools) ---------------- */
+
+/* Reference matrices of the library's basis (Sec. II-A): K [3][B][B] with
+ * K[c][b][bb] = int phi_b d(phi_bb)/d xi_c and Ft [4][B][F] with
+ * Ft[i][b][f] = int_{face i} phi_b psi_f over the unit triangle, face i
+ * opposite local vertex i parameterised by its vertices in ascending order. */
+int edg_reference_matrices(int32_t order, double* K, double* Ft);
+
+/* Clustering of Sec. IV-A on host data: dt [K] CFL steps, nbr [K][4] face
+ * neighbours (-1 = none); writes cluster [K] (1..N_c), lambda and speedup.
+ * lambda_in <= 0 searches. */
+int edg_cluster_host(int64_t K, const double* dt, const int64_t* nbr, int32_t n_clusters,
+                     double lambda_in, int32_t* cluster, double* lambda_out, double* speedup_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,939 @@
+// Host side of the C-ABI (include/edge_lts.h): mesh processing, geometry,
+// clusters, reordering, per-element tables, DOF conversion, the LTS level
+// loop and device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "basis.hpp"
+#include "edge_lts.h"
+#include "kernels.hpp"
+
+using namespace edg;
+
+namespace {
+constexpr int EPW = 7;
+constexpr int LPE = 9;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+}  // namespace
+
+struct edg_ctx {
+  edg_config cfg{};
+  int O = 0, B = 0, F = 0, FP = 0, M = 0, NQ = 0;
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  // mesh, caller's element order; faces indexed in the sorted-vertex frame
+  int64_t K = 0;
+  std::vector<std::array<int, 4>> perm;  // sorted local vertex m = caller's local vertex perm[m]
+  std::vector<int64_t> nbr, nbr_face;    // [K][4]
+  std::vector<int8_t> bc;                // [K][4]
+  std::vector<double> Gm, absdet, inradius, normals, areas, X;  // X: sorted coords [K][4][3]
+  bool have_mesh = false, have_mat = false, have_clusters = false;
+
+  std::vector<double> rho, vp, vs, yp, ys, omega;
+
+  std::vector<int> cl;  // 0-based cluster per caller element
+  double dt_min = 0, lam = 1, speedup = 1;
+  std::vector<int64_t> internal_to_user, user_to_internal;
+  int cl_end[MAX_CLUSTERS] = {0};
+  double dt_cl[MAX_CLUSTERS] = {0};
+  int64_t level = 0;
+  int64_t nstep[MAX_CLUSTERS] = {0};
+  int64_t updates = 0;
+
+  int64_t G = 0, Kp = 0;
+  DevBuf Qe, Qa, P, FI, EF, T1, T2, T3, RecSlot, RecD;
+  // sources
+  int n_src = 0;
+  DevBuf s_elem, s_kind, s_par, s_mom, s_phi, s_idet;
+  // receivers
+  int n_rec = 0;
+  int64_t rec_ns = 0;
+  double rec_dt = 0;
+  DevBuf r_elem, r_slot, r_phi, r_out;
+
+  std::vector<std::vector<double>> perm_mats;  // 24 B x B conversion matrices
+
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int64_t> ev_updates;
+  int64_t t_launches = 0, t_updates = 0;
+  double t_ms = 0;
+
+  ~edg_ctx();
+};
+
+namespace {
+
+int fail(edg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(ctx, EDG_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void dev_free(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+int dev_alloc(edg_ctx* c, DevBuf& b, size_t bytes) {
+  dev_free(b);
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(c, EDG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return 0;
+}
+
+int dev_upload(edg_ctx* c, DevBuf& b, const void* src, size_t bytes) {
+  int rc = dev_alloc(c, b, bytes);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+  return 0;
+}
+
+int perm_code(const std::array<int, 4>& p) {
+  // lexicographic rank of the permutation (0..23)
+  int code = 0;
+  const int fact[4] = {6, 2, 1, 1};
+  bool used[4] = {false, false, false, false};
+  for (int m = 0; m < 4; ++m) {
+    int r = 0;
+    for (int v = 0; v < p[m]; ++v)
+      if (!used[v]) ++r;
+    code += r * fact[m];
+    used[p[m]] = true;
+  }
+  return code;
+}
+
+const std::vector<double>& perm_matrix(edg_ctx* c, const std::array<int, 4>& p) {
+  if (c->perm_mats.empty()) c->perm_mats.resize(24);
+  auto& m = c->perm_mats[perm_code(p)];
+  if (m.empty()) m = vertex_permutation_matrix(c->O, p.data());
+  return m;
+}
+
+void inverse3(const double J[9], double G[9], double& det) {
+  det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) + J[2] * (J[3] * J[7] - J[4] * J[6]);
+  const double id = 1.0 / det;
+  G[0] = (J[4] * J[8] - J[5] * J[7]) * id;
+  G[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+  G[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+  G[3] = (J[5] * J[6] - J[3] * J[8]) * id;
+  G[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+  G[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+  G[6] = (J[3] * J[7] - J[4] * J[6]) * id;
+  G[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+  G[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+}
+
+// Sec. IV-A clustering: assign by interval, normalise to the neighbour rule,
+// optional lambda search maximising K / sum_l n_l / (2^(l-1) lambda).
+void cluster_assign(int64_t K, const double* dt, double dt_min, double lam, int Nc, std::vector<int>& cl) {
+  cl.assign(K, 0);
+  const double base = lam * dt_min;
+  for (int64_t k = 0; k < K; ++k)
+    for (int l = 1; l < Nc; ++l)
+      if (dt[k] >= std::ldexp(base, l)) cl[k] = l;
+}
+
+void cluster_normalise(int64_t K, const int64_t* nbr, std::vector<int>& cl) {
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    std::vector<int> nw(cl);
+    for (int64_t k = 0; k < K; ++k) {
+      int mn = 1 << 30;
+      for (int i = 0; i < 4; ++i) {
+        const int64_t n = nbr[k * 4 + i];
+        if (n >= 0) mn = std::min(mn, cl[n]);
+      }
+      if (mn + 1 < nw[k]) {
+        nw[k] = mn + 1;
+        changed = true;
+      }
+    }
+    cl.swap(nw);
+  }
+}
+
+double cluster_speedup(const std::vector<int>& cl, double lam, int Nc) {
+  std::vector<int64_t> cnt(Nc, 0);
+  for (int v : cl) cnt[v]++;
+  double denom = 0.0;
+  for (int l = 0; l < Nc; ++l) denom += (double)cnt[l] / (std::ldexp(1.0, l) * lam);
+  return (double)cl.size() / denom;
+}
+
+void cluster_all(int64_t K, const double* dt, const int64_t* nbr, int Nc, double lam_in, std::vector<int>& cl,
+                 double& lam_out, double& speed) {
+  double dt_min = dt[0];
+  for (int64_t k = 1; k < K; ++k) dt_min = std::min(dt_min, dt[k]);
+  if (lam_in > 0) {
+    cluster_assign(K, dt, dt_min, lam_in, Nc, cl);
+    cluster_normalise(K, nbr, cl);
+    lam_out = lam_in;
+    speed = cluster_speedup(cl, lam_in, Nc);
+    return;
+  }
+  bool first = true;
+  for (int i = 51; i <= 100; ++i) {
+    const double lm = i / 100.0;
+    std::vector<int> c;
+    cluster_assign(K, dt, dt_min, lm, Nc, c);
+    cluster_normalise(K, nbr, c);
+    const double s = cluster_speedup(c, lm, Nc);
+    if (first || s >= speed) {
+      cl.swap(c);
+      lam_out = lm;
+      speed = s;
+      first = false;
+    }
+  }
+}
+
+template <class R>
+void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vector<int>& EF) {
+  const int64_t Kp = c->Kp;
+  P.assign((size_t)Kp * NPARAM, R(0));
+  FI.assign((size_t)Kp * 8, 0);
+  EF.assign((size_t)Kp, 0);
+  for (int64_t ki = 0; ki < Kp; ++ki) {
+    const int64_t k = c->internal_to_user[ki < c->K ? ki : 0];
+    R* p = &P[(size_t)ki * NPARAM];
+    const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
+    const double mu = rho * vs * vs, lam = rho * vp * vp - 2.0 * mu;
+    for (int j = 0; j < 9; ++j) p[j] = R(c->Gm[k * 9 + j]);
+    p[9] = R(1.0 / rho);
+    p[10] = R(lam);
+    p[11] = R(mu);
+    p[12] = R(rho * vp);
+    p[13] = R(rho * vs);
+    for (int l = 0; l < c->M; ++l) {
+      const double ypl = c->yp[k * c->M + l], ysl = c->ys[k * c->M + l];
+      p[14 + 2 * l] = R((lam + 2.0 * mu) * ypl - 2.0 * mu * ysl);
+      p[15 + 2 * l] = R(2.0 * mu * ysl);
+    }
+    int flags = 0;
+    for (int i = 0; i < 4; ++i) {
+      R* f = p + 20 + 6 * i;
+      for (int d = 0; d < 3; ++d) f[d] = R(c->normals[(k * 4 + i) * 3 + d]);
+      f[3] = R(2.0 * c->areas[k * 4 + i] / c->absdet[k]);
+      const int64_t n = c->nbr[k * 4 + i];
+      int nb_int = -1, j = 0, rel = 0, bc = c->bc[k * 4 + i];
+      if (n >= 0) {
+        f[4] = R(c->rho[n] * c->vp[n]);
+        f[5] = R(c->rho[n] * c->vs[n]);
+        nb_int = (int)c->user_to_internal[n];
+        j = (int)c->nbr_face[k * 4 + i];
+        rel = c->cl[n] - c->cl[k];
+        bc = 0;
+        if (rel < 0) flags |= EF_HAS_FINER;
+        if (rel > 0) flags |= EF_HAS_COARSER;
+      } else {
+        f[4] = R(rho * vp);
+        f[5] = R(rho * vs);
+      }
+      if (ki >= c->K) {  // padding: boundary faces, never written
+        nb_int = -1;
+        bc = EDG_BC_ABSORB;
+        rel = 0;
+      }
+      FI[(size_t)ki * 8 + 2 * i] = nb_int;
+      FI[(size_t)ki * 8 + 2 * i + 1] = j | (bc << 4) | ((rel + 1) << 8);
+    }
+    EF[(size_t)ki] = ki < c->K ? flags : 0;
+  }
+}
+
+// DOF layout: elastic [G][B][63] (slot 9e+q), memory [G][B][m][42] (slot 6e+q)
+inline size_t qe_index(const edg_ctx* c, int64_t ki, int q, int b) {
+  return ((size_t)(ki / EPW) * c->B + b) * (EPW * LPE) + (ki % EPW) * LPE + q;
+}
+inline size_t qa_index(const edg_ctx* c, int64_t ki, int l, int q, int b) {
+  return (((size_t)(ki / EPW) * c->B + b) * c->M + l) * (EPW * 6) + (ki % EPW) * 6 + q;
+}
+
+template <class R>
+int set_dofs_t(edg_ctx* c, const double* dofs) {
+  const int B = c->B, NQ = c->NQ;
+  std::vector<R> he((size_t)c->G * B * EPW * LPE, R(0));
+  std::vector<R> ha(c->M > 0 ? (size_t)c->G * B * c->M * EPW * 6 : 1, R(0));
+  std::vector<double> row(B);
+  for (int64_t k = 0; k < c->K; ++k) {
+    const int64_t ki = c->user_to_internal[k];
+    const auto& C = perm_matrix(c, c->perm[k]);
+    for (int q = 0; q < NQ; ++q) {
+      const double* src = dofs + ((size_t)k * NQ + q) * B;
+      for (int b = 0; b < B; ++b) {
+        double s = 0.0;
+        for (int bb = 0; bb < B; ++bb) s += C[b * B + bb] * src[bb];
+        row[b] = s;
+      }
+      for (int b = 0; b < B; ++b) {
+        if (q < 9) he[qe_index(c, ki, q, b)] = R(row[b]);
+        else ha[qa_index(c, ki, (q - 9) / 6, (q - 9) % 6, b)] = R(row[b]);
+      }
+    }
+  }
+  HIPCHK(c, hipMemcpy(c->Qe.p, he.data(), he.size() * sizeof(R), hipMemcpyHostToDevice));
+  if (c->M > 0) HIPCHK(c, hipMemcpy(c->Qa.p, ha.data(), ha.size() * sizeof(R), hipMemcpyHostToDevice));
+  return 0;
+}
+
+template <class R>
+int get_dofs_t(edg_ctx* c, double* out) {
+  const int B = c->B, NQ = c->NQ;
+  std::vector<R> he((size_t)c->G * B * EPW * LPE);
+  std::vector<R> ha(c->M > 0 ? (size_t)c->G * B * c->M * EPW * 6 : 1);
+  HIPCHK(c, hipMemcpy(he.data(), c->Qe.p, he.size() * sizeof(R), hipMemcpyDeviceToHost));
+  if (c->M > 0) HIPCHK(c, hipMemcpy(ha.data(), c->Qa.p, ha.size() * sizeof(R), hipMemcpyDeviceToHost));
+  std::vector<double> row(B);
+  for (int64_t k = 0; k < c->K; ++k) {
+    const int64_t ki = c->user_to_internal[k];
+    const auto& C = perm_matrix(c, c->perm[k]);
+    for (int q = 0; q < NQ; ++q) {
+      for (int b = 0; b < B; ++b)
+        row[b] = q < 9 ? (double)he[qe_index(c, ki, q, b)] : (double)ha[qa_index(c, ki, (q - 9) / 6, (q - 9) % 6, b)];
+      double* dst = out + ((size_t)k * NQ + q) * B;
+      for (int bb = 0; bb < B; ++bb) {
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += C[b * B + bb] * row[b];
+        dst[bb] = s;
+      }
+    }
+  }
+  return 0;
+}
+
+// locate a point: lowest caller element index whose barycentrics are >= -tol
+int64_t locate(const edg_ctx* c, const double* x, double xi_sorted[3]) {
+  const double tol = 1e-10;
+  for (int64_t k = 0; k < c->K; ++k) {
+    const double* X = &c->X[(size_t)k * 12];
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(std::min(X[d], X[3 + d]), std::min(X[6 + d], X[9 + d]));
+      hi[d] = std::max(std::max(X[d], X[3 + d]), std::max(X[6 + d], X[9 + d]));
+      const double pad = 1e-9 * (hi[d] - lo[d] + 1.0);
+      lo[d] -= pad;
+      hi[d] += pad;
+    }
+    if (x[0] < lo[0] || x[0] > hi[0] || x[1] < lo[1] || x[1] > hi[1] || x[2] < lo[2] || x[2] > hi[2]) continue;
+    const double* G = &c->Gm[(size_t)k * 9];
+    double r[3];
+    for (int cc = 0; cc < 3; ++cc) {
+      r[cc] = 0.0;
+      for (int d = 0; d < 3; ++d) r[cc] += G[cc * 3 + d] * (x[d] - X[d]);
+    }
+    if (r[0] >= -tol && r[1] >= -tol && r[2] >= -tol && 1.0 - r[0] - r[1] - r[2] >= -tol) {
+      for (int d = 0; d < 3; ++d) xi_sorted[d] = r[d];
+      return k;
+    }
+  }
+  return -1;
+}
+
+template <class R, int O, int M>
+struct Launch {
+  static int level(const KPtrs& p, const LevelArgs& a, hipStream_t s) { return launch_level<R, O, M>(p, a, s); }
+  static int src(const KPtrs& p, const LevelArgs& a, const SrcArgs& sa, hipStream_t s) {
+    return launch_sources<R, O, M>(p, a, sa, s);
+  }
+  static int rec(const KPtrs& p, const LevelArgs& a, const RecArgs& ra, hipStream_t s) {
+    return launch_receivers<R, O, M>(p, a, ra, s);
+  }
+};
+
+typedef int (*LevelFn)(const KPtrs&, const LevelArgs&, hipStream_t);
+typedef int (*SrcFn)(const KPtrs&, const LevelArgs&, const SrcArgs&, hipStream_t);
+typedef int (*RecFn)(const KPtrs&, const LevelArgs&, const RecArgs&, hipStream_t);
+
+struct Fns {
+  LevelFn level = nullptr;
+  SrcFn src = nullptr;
+  RecFn rec = nullptr;
+};
+
+Fns pick(int fp64, int O, int M) {
+  Fns f;
+#define EDG_PICK(R, OO, MM)                                                         \
+  if ((std::is_same<R, double>::value == (fp64 != 0)) && O == OO && M == MM) {      \
+    f.level = &Launch<R, OO, MM>::level;                                            \
+    f.src = &Launch<R, OO, MM>::src;                                                \
+    f.rec = &Launch<R, OO, MM>::rec;                                                \
+  }
+  EDG_FOR_EACH_VARIANT(EDG_PICK)
+#undef EDG_PICK
+  return f;
+}
+
+KPtrs kptrs(const edg_ctx* c) {
+  KPtrs p;
+  p.Qe = c->Qe.p;
+  p.Qa = c->Qa.p;
+  p.P = c->P.p;
+  p.FI = (const int*)c->FI.p;
+  p.EF = (const int*)c->EF.p;
+  p.T1 = c->T1.p;
+  p.T2 = c->T2.p;
+  p.T3 = c->T3.p;
+  p.rec_slot = (const int*)c->RecSlot.p;
+  p.recD = c->RecD.p;
+  p.Kp = c->Kp;
+  return p;
+}
+
+LevelArgs base_args(const edg_ctx* c) {
+  LevelArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.n_clusters = c->cfg.n_clusters;
+  for (int l = 0; l < MAX_CLUSTERS; ++l) {
+    a.cl_end[l] = l < c->cfg.n_clusters ? c->cl_end[l] : (int)c->K;
+    a.dt[l] = c->dt_cl[l];
+    for (int d = 0; d < c->O; ++d) {
+      double f = 1.0;
+      for (int j = 2; j <= d + 1; ++j) f *= j;
+      a.tc[l][d] = std::pow(c->dt_cl[l], d + 1) / f;
+      a.th[l][d] = std::pow(0.5 * c->dt_cl[l], d + 1) / f;
+    }
+  }
+  for (int l = 0; l < c->M; ++l) a.omega[l] = c->omega[l];
+  return a;
+}
+
+int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, int64_t upd) {
+  if (c->timing) {
+    if (c->ev_used == c->ev_pool.size()) {
+      hipEvent_t e0, e1;
+      HIPCHK(c, hipEventCreate(&e0));
+      HIPCHK(c, hipEventCreate(&e1));
+      c->ev_pool.push_back({e0, e1});
+    }
+    auto& ev = c->ev_pool[c->ev_used++];
+    c->ev_updates.push_back(upd);
+    HIPCHK(c, hipEventRecord(ev.first, c->stream));
+    int rc = fn.level(p, a, c->stream);
+    if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
+    HIPCHK(c, hipEventRecord(ev.second, c->stream));
+    return 0;
+  }
+  int rc = fn.level(p, a, c->stream);
+  if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return 0;
+}
+
+}  // namespace
+
+edg_ctx::~edg_ctx() {
+  for (DevBuf* b : {&Qe, &Qa, &P, &FI, &EF, &T1, &T2, &T3, &RecSlot, &RecD, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
+                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out})
+    dev_free(*b);
+  for (auto& e : ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+extern "C" {
+
+int edg_create(const edg_config* cfg, edg_ctx** out) {
+  if (!out) return EDG_EINVAL;
+  *out = nullptr;
+  if (!cfg) return EDG_EINVAL;
+  if (cfg->order < 2 || cfg->order > MAX_ORDER) return EDG_EINVAL;
+  if (!(cfg->mechanisms == 0 || cfg->mechanisms == 3)) return EDG_EINVAL;
+  if (cfg->n_runs != 1) return EDG_EINVAL;
+  if (cfg->n_clusters < 1 || cfg->n_clusters > MAX_CLUSTERS) return EDG_EINVAL;
+  if (!(cfg->cfl > 0) || cfg->lambda > 1.0 || (cfg->lambda > 0 && cfg->lambda <= 0.5)) return EDG_EINVAL;
+  if (!pick(cfg->fp64, cfg->order, cfg->mechanisms).level) return EDG_EINVAL;
+  if (hipSetDevice(cfg->device) != hipSuccess) return EDG_EHIP;
+  edg_ctx* c = new (std::nothrow) edg_ctx;
+  if (!c) return EDG_ENOMEM;
+  c->cfg = *cfg;
+  c->O = cfg->order;
+  c->B = n_basis(c->O);
+  c->F = n_face_basis(c->O);
+  c->FP = (c->F + 3) / 4 * 4;
+  c->M = cfg->mechanisms;
+  c->NQ = 9 + 6 * c->M;
+  if (cfg->hip_stream) {
+    c->stream = (hipStream_t)cfg->hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return EDG_EHIP;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return EDG_OK;
+}
+
+int edg_upload_mesh(edg_ctx* c, int64_t K, const int64_t* tv, const double* xyz, const int8_t* face_bc) {
+  if (!c) return EDG_EINVAL;
+  if (K <= 0 || !tv || !xyz) return fail(c, EDG_EINVAL, "empty mesh or null arrays");
+  if (K > (int64_t)0x7fffffff / 8) return fail(c, EDG_EINVAL, "too many tets");
+  c->K = K;
+  c->perm.assign(K, {0, 1, 2, 3});
+  c->nbr.assign(K * 4, -1);
+  c->nbr_face.assign(K * 4, -1);
+  c->bc.assign(K * 4, 0);
+  c->Gm.assign(K * 9, 0.0);
+  c->absdet.assign(K, 0.0);
+  c->inradius.assign(K, 0.0);
+  c->normals.assign(K * 12, 0.0);
+  c->areas.assign(K * 4, 0.0);
+  c->X.assign(K * 12, 0.0);
+  c->have_mesh = c->have_mat = c->have_clusters = false;
+  struct FaceKey {
+    int64_t a, b, cc, id;
+  };
+  std::vector<FaceKey> faces((size_t)K * 4);
+  for (int64_t k = 0; k < K; ++k) {
+    std::array<int, 4>& p = c->perm[k];
+    std::sort(p.begin(), p.end(), [&](int x, int y) { return tv[k * 4 + x] < tv[k * 4 + y]; });
+    for (int m = 0; m + 1 < 4; ++m)
+      if (tv[k * 4 + p[m]] == tv[k * 4 + p[m + 1]])
+        return fail(c, EDG_EMESH, "tet " + std::to_string(k) + " repeats a vertex id");
+    for (int m = 0; m < 4; ++m)
+      for (int d = 0; d < 3; ++d) c->X[k * 12 + m * 3 + d] = xyz[(k * 4 + p[m]) * 3 + d];
+    for (int i = 0; i < 4; ++i) {
+      int64_t v[3], n = 0;
+      for (int m = 0; m < 4; ++m)
+        if (m != i) v[n++] = tv[k * 4 + p[m]];
+      faces[k * 4 + i] = {v[0], v[1], v[2], k * 4 + i};
+      c->bc[k * 4 + i] = face_bc ? face_bc[k * 4 + p[i]] : 0;
+    }
+    // geometry in the sorted frame
+    const double* X = &c->X[k * 12];
+    double J[9], Gi[9], det;
+    for (int d = 0; d < 3; ++d)
+      for (int m = 0; m < 3; ++m) J[d * 3 + m] = X[(m + 1) * 3 + d] - X[d];
+    inverse3(J, Gi, det);
+    if (!(std::fabs(det) > 0) || !std::isfinite(det)) return fail(c, EDG_EMESH, "degenerate tet " + std::to_string(k));
+    for (int j = 0; j < 9; ++j) c->Gm[k * 9 + j] = Gi[j];
+    c->absdet[k] = std::fabs(det);
+    double asum = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      int a[3], n = 0;
+      for (int m = 0; m < 4; ++m)
+        if (m != i) a[n++] = m;
+      double e1[3], e2[3], cr[3];
+      for (int d = 0; d < 3; ++d) {
+        e1[d] = X[a[1] * 3 + d] - X[a[0] * 3 + d];
+        e2[d] = X[a[2] * 3 + d] - X[a[0] * 3 + d];
+      }
+      cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      const double nrm = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      double s = 0.0;
+      for (int d = 0; d < 3; ++d) s += cr[d] * (X[i * 3 + d] - X[a[0] * 3 + d]);
+      const double sg = s > 0 ? -1.0 : 1.0;
+      for (int d = 0; d < 3; ++d) c->normals[(k * 4 + i) * 3 + d] = sg * cr[d] / nrm;
+      c->areas[k * 4 + i] = 0.5 * nrm;
+      asum += 0.5 * nrm;
+    }
+    c->inradius[k] = 3.0 * (c->absdet[k] / 6.0) / asum;
+  }
+  std::sort(faces.begin(), faces.end(), [](const FaceKey& x, const FaceKey& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.cc != y.cc) return x.cc < y.cc;
+    return x.id < y.id;
+  });
+  for (size_t s = 0; s < faces.size();) {
+    size_t e = s + 1;
+    while (e < faces.size() && faces[e].a == faces[s].a && faces[e].b == faces[s].b && faces[e].cc == faces[s].cc) ++e;
+    if (e - s > 2) return fail(c, EDG_EMESH, "a face is shared by more than two tets");
+    if (e - s == 2) {
+      const int64_t f0 = faces[s].id, f1 = faces[s + 1].id;
+      if (c->bc[f0] != 0 || c->bc[f1] != 0) return fail(c, EDG_EMESH, "a matched face carries a boundary tag");
+      c->nbr[f0] = f1 / 4;
+      c->nbr_face[f0] = f1 % 4;
+      c->nbr[f1] = f0 / 4;
+      c->nbr_face[f1] = f0 % 4;
+    } else {
+      const int64_t f0 = faces[s].id;
+      if (c->bc[f0] != EDG_BC_FREE && c->bc[f0] != EDG_BC_ABSORB)
+        return fail(c, EDG_EMESH, "face " + std::to_string(f0 % 4) + " of tet " + std::to_string(f0 / 4) +
+                                      " has no neighbour and no boundary tag");
+    }
+    s = e;
+  }
+  c->have_mesh = true;
+  return EDG_OK;
+}
+
+int edg_upload_materials(edg_ctx* c, const double* rho, const double* vp, const double* vs, const double* omega,
+                         const double* yp, const double* ys) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_mesh) return fail(c, EDG_ESTATE, "upload the mesh first");
+  if (!rho || !vp || !vs) return fail(c, EDG_EINVAL, "null material array");
+  if (c->M > 0 && (!omega || !yp || !ys)) return fail(c, EDG_EINVAL, "anelastic run needs omega, yp, ys");
+  const int64_t K = c->K;
+  for (int64_t k = 0; k < K; ++k)
+    if (!(rho[k] > 0) || !(vs[k] > 0) || !(vp[k] > std::sqrt(4.0 / 3.0) * vs[k]))
+      return fail(c, EDG_EINVAL, "material of element " + std::to_string(k) + " out of range");
+  c->rho.assign(rho, rho + K);
+  c->vp.assign(vp, vp + K);
+  c->vs.assign(vs, vs + K);
+  if (c->M > 0) {
+    c->omega.assign(omega, omega + c->M);
+    c->yp.assign(yp, yp + K * c->M);
+    c->ys.assign(ys, ys + K * c->M);
+  } else {
+    c->omega.clear();
+  }
+  c->have_mat = true;
+  if (c->have_clusters) {  // re-derive operators, keep clusters and state
+    if (c->cfg.fp64) {
+      std::vector<double> P;
+      std::vector<int> FI, EF;
+      pack_tables<double>(c, P, FI, EF);
+      HIPCHK(c, hipMemcpy(c->P.p, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> P;
+      std::vector<int> FI, EF;
+      pack_tables<float>(c, P, FI, EF);
+      HIPCHK(c, hipMemcpy(c->P.p, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+  }
+  return EDG_OK;
+}
+
+int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_mesh || !c->have_mat) return fail(c, EDG_ESTATE, "upload mesh and materials first");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const int64_t K = c->K;
+  const int Nc = c->cfg.n_clusters, O = c->O;
+  std::vector<double> dt(K);
+  for (int64_t k = 0; k < K; ++k) dt[k] = c->cfg.cfl * 2.0 * c->inradius[k] / ((2.0 * (O - 1) + 1.0) * c->vp[k]);
+  c->dt_min = *std::min_element(dt.begin(), dt.end());
+  if (cluster) {
+    c->cl.assign(K, 0);
+    for (int64_t k = 0; k < K; ++k) {
+      if (cluster[k] < 1 || cluster[k] > Nc) return fail(c, EDG_EINVAL, "cluster id out of range");
+      c->cl[k] = cluster[k] - 1;
+    }
+    for (int64_t k = 0; k < K; ++k)
+      for (int i = 0; i < 4; ++i) {
+        const int64_t n = c->nbr[k * 4 + i];
+        if (n >= 0 && std::abs(c->cl[n] - c->cl[k]) > 1)
+          return fail(c, EDG_EINVAL, "face neighbours differ by more than one cluster");
+      }
+    c->lam = c->cfg.lambda > 0 ? c->cfg.lambda : 1.0;
+    c->speedup = cluster_speedup(c->cl, c->lam, Nc);
+  } else {
+    cluster_all(K, dt.data(), c->nbr.data(), Nc, c->cfg.lambda, c->cl, c->lam, c->speedup);
+  }
+  for (int l = 0; l < MAX_CLUSTERS; ++l) c->dt_cl[l] = std::ldexp(c->lam * c->dt_min, l);
+  // reorder: by cluster, then caller order
+  c->internal_to_user.resize(K);
+  std::iota(c->internal_to_user.begin(), c->internal_to_user.end(), 0);
+  std::stable_sort(c->internal_to_user.begin(), c->internal_to_user.end(),
+                   [&](int64_t a, int64_t b) { return c->cl[a] < c->cl[b]; });
+  c->user_to_internal.resize(K);
+  for (int64_t ki = 0; ki < K; ++ki) c->user_to_internal[c->internal_to_user[ki]] = ki;
+  for (int l = 0; l < MAX_CLUSTERS; ++l) c->cl_end[l] = 0;
+  for (int64_t k = 0; k < K; ++k)
+    for (int l = c->cl[k]; l < MAX_CLUSTERS; ++l) c->cl_end[l]++;
+  // device state
+  c->G = (K + EPW - 1) / EPW;
+  c->Kp = c->G * EPW;
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  int rc;
+  if ((rc = dev_alloc(c, c->Qe, (size_t)c->G * c->B * EPW * LPE * rs))) return rc;
+  if ((rc = dev_alloc(c, c->Qa, c->M > 0 ? (size_t)c->G * c->B * c->M * EPW * 6 * rs : 16))) return rc;
+  const size_t tb = (size_t)2 * c->Kp * 4 * LPE * c->FP * rs;
+  if ((rc = dev_alloc(c, c->T1, tb))) return rc;
+  if ((rc = dev_alloc(c, c->T2, tb))) return rc;
+  if ((rc = dev_alloc(c, c->T3, tb))) return rc;
+  HIPCHK(c, hipMemset(c->Qe.p, 0, c->Qe.bytes));
+  HIPCHK(c, hipMemset(c->Qa.p, 0, c->Qa.bytes));
+  HIPCHK(c, hipMemset(c->T1.p, 0, tb));
+  HIPCHK(c, hipMemset(c->T2.p, 0, tb));
+  HIPCHK(c, hipMemset(c->T3.p, 0, tb));
+  std::vector<int> FI, EF;
+  if (c->cfg.fp64) {
+    std::vector<double> P;
+    pack_tables<double>(c, P, FI, EF);
+    if ((rc = dev_upload(c, c->P, P.data(), P.size() * sizeof(double)))) return rc;
+  } else {
+    std::vector<float> P;
+    pack_tables<float>(c, P, FI, EF);
+    if ((rc = dev_upload(c, c->P, P.data(), P.size() * sizeof(float)))) return rc;
+  }
+  if ((rc = dev_upload(c, c->FI, FI.data(), FI.size() * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->EF, EF.data(), EF.size() * sizeof(int)))) return rc;
+  std::vector<int> rs_slot((size_t)c->Kp, -1);
+  if ((rc = dev_upload(c, c->RecSlot, rs_slot.data(), rs_slot.size() * sizeof(int)))) return rc;
+  c->level = 0;
+  for (int l = 0; l < MAX_CLUSTERS; ++l) c->nstep[l] = 0;
+  c->updates = 0;
+  c->have_clusters = true;
+  return EDG_OK;
+}
+
+int edg_get_clusters(const edg_ctx* c, int32_t* cl_out, double* dt_min, double* lam, double* sync_dt, double* sp) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return EDG_ESTATE;
+  if (cl_out)
+    for (int64_t k = 0; k < c->K; ++k) cl_out[k] = c->cl[k] + 1;
+  if (dt_min) *dt_min = c->dt_min;
+  if (lam) *lam = c->lam;
+  if (sync_dt) *sync_dt = c->dt_cl[c->cfg.n_clusters - 1];
+  if (sp) *sp = c->speedup;
+  return EDG_OK;
+}
+
+int edg_set_initial(edg_ctx* c, int32_t run, const double* dofs) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (run != 0 || !dofs) return fail(c, EDG_EINVAL, "bad run or null dofs");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  return c->cfg.fp64 ? set_dofs_t<double>(c, dofs) : set_dofs_t<float>(c, dofs);
+}
+
+int edg_read_dofs(edg_ctx* c, int32_t run, double* out, int64_t cap) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (run != 0 || !out) return fail(c, EDG_EINVAL, "bad run or null output");
+  if (cap < c->K * c->NQ * c->B) return fail(c, EDG_ECAP, "output capacity too small");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  return c->cfg.fp64 ? get_dofs_t<double>(c, out) : get_dofs_t<float>(c, out);
+}
+
+int edg_set_sources(edg_ctx* c, int32_t run, int64_t n, const double* xyz, const double* moment, int32_t kind,
+                    const double* par) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (run != 0 || n < 0 || (n > 0 && (!xyz || !moment || !par))) return fail(c, EDG_EINVAL, "bad source arguments");
+  if (kind != EDG_STF_RICKER && kind != EDG_STF_HANN) return fail(c, EDG_EINVAL, "unknown source time function");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  std::vector<int> el(n), kd(n, kind);
+  std::vector<double> phi((size_t)n * c->B), idet(n);
+  for (int64_t s = 0; s < n; ++s) {
+    double xi[3];
+    const int64_t k = locate(c, xyz + 3 * s, xi);
+    if (k < 0) return fail(c, EDG_EINVAL, "source " + std::to_string(s) + " is outside the mesh");
+    el[s] = (int)c->user_to_internal[k];
+    auto v = eval_basis(c->O, xi);
+    std::copy(v.begin(), v.end(), phi.begin() + s * c->B);
+    idet[s] = 1.0 / c->absdet[k];
+  }
+  int rc;
+  if ((rc = dev_upload(c, c->s_elem, el.data(), n * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->s_kind, kd.data(), n * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->s_par, par, n * 2 * sizeof(double)))) return rc;
+  if ((rc = dev_upload(c, c->s_mom, moment, n * 6 * sizeof(double)))) return rc;
+  if ((rc = dev_upload(c, c->s_phi, phi.data(), phi.size() * sizeof(double)))) return rc;
+  if ((rc = dev_upload(c, c->s_idet, idet.data(), n * sizeof(double)))) return rc;
+  c->n_src = (int)n;
+  return EDG_OK;
+}
+
+int edg_set_receivers(edg_ctx* c, int64_t n, const double* xyz, double dt_sample, int64_t ns) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (n < 0 || (n > 0 && (!xyz || !(dt_sample > 0) || ns <= 0))) return fail(c, EDG_EINVAL, "bad receiver arguments");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  std::vector<int> el(n), slot(n), rs_slot((size_t)c->Kp, -1);
+  std::vector<double> phi((size_t)n * c->B);
+  int nslots = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    double xi[3];
+    const int64_t k = locate(c, xyz + 3 * r, xi);
+    if (k < 0) return fail(c, EDG_EINVAL, "receiver " + std::to_string(r) + " is outside the mesh");
+    const int64_t ki = c->user_to_internal[k];
+    el[r] = (int)ki;
+    if (rs_slot[ki] < 0) rs_slot[ki] = nslots++;
+    slot[r] = rs_slot[ki];
+    auto v = eval_basis(c->O, xi);
+    std::copy(v.begin(), v.end(), phi.begin() + r * c->B);
+  }
+  int rc;
+  if ((rc = dev_upload(c, c->RecSlot, rs_slot.data(), rs_slot.size() * sizeof(int)))) return rc;
+  const size_t rsz = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  if ((rc = dev_alloc(c, c->RecD, (size_t)std::max(nslots, 1) * c->O * LPE * c->B * rsz))) return rc;
+  if ((rc = dev_upload(c, c->r_elem, el.data(), n * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->r_slot, slot.data(), n * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->r_phi, phi.data(), phi.size() * sizeof(double)))) return rc;
+  if ((rc = dev_alloc(c, c->r_out, (size_t)std::max<int64_t>(n, 1) * ns * LPE * sizeof(double)))) return rc;
+  HIPCHK(c, hipMemset(c->r_out.p, 0, c->r_out.bytes));
+  c->n_rec = (int)n;
+  c->rec_ns = ns;
+  c->rec_dt = dt_sample;
+  return EDG_OK;
+}
+
+int edg_advance_to(edg_ctx* c, double t) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const int Nc = c->cfg.n_clusters;
+  const double sync = c->dt_cl[Nc - 1];
+  const double t_now = (double)c->level * c->dt_cl[0];
+  const double cycles = (t - t_now) / sync;
+  const double nc = std::nearbyint(cycles);
+  if (nc < 0 || std::fabs(cycles - nc) > 1e-9 * std::max(1.0, std::fabs(cycles)))
+    return fail(c, EDG_ENOTSYNC, "time is not a synchronisation point after the current time");
+  if (nc == 0) return EDG_OK;
+  const int64_t per = (int64_t)1 << (Nc - 1);
+  const int64_t L = (int64_t)nc * per;
+  const Fns fn = pick(c->cfg.fp64, c->O, c->M);
+  const KPtrs p = kptrs(c);
+  SrcArgs sa;
+  sa.n = c->n_src;
+  sa.elem = (const int*)c->s_elem.p;
+  sa.kind = (const int*)c->s_kind.p;
+  sa.par = (const double*)c->s_par.p;
+  sa.moment = (const double*)c->s_mom.p;
+  sa.phi = (const double*)c->s_phi.p;
+  sa.inv_det = (const double*)c->s_idet.p;
+  RecArgs ra;
+  ra.n = c->n_rec;
+  ra.elem = (const int*)c->r_elem.p;
+  ra.slot = (const int*)c->r_slot.p;
+  ra.phi = (const double*)c->r_phi.p;
+  ra.dt_sample = c->rec_dt;
+  ra.ns = c->rec_ns;
+  ra.out = (double*)c->r_out.p;
+  c->ev_used = 0;
+  c->ev_updates.clear();
+
+  LevelArgs a = base_args(c);
+  a.kind = KIND_PREDICT;
+  a.end = (int)c->K;
+  for (int l = 0; l < Nc; ++l) a.step_new[l] = (int)c->nstep[l];
+  int rc = launch_timed(c, fn, p, a, 0);
+  if (rc) return rc;
+  if (c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->stream)))
+    return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
+  for (int64_t j = 1; j <= L; ++j) {
+    const int64_t g = c->level + j;
+    int lmax = 0;
+    for (int l = 1; l < Nc; ++l)
+      if (g % ((int64_t)1 << l) == 0) lmax = l;
+    a = base_args(c);
+    a.end = c->cl_end[lmax];
+    for (int l = 0; l <= lmax; ++l) {
+      a.step_fin[l] = (int)c->nstep[l];
+      a.step_new[l] = (int)c->nstep[l] + 1;
+    }
+    if (c->n_src > 0 && (rc = fn.src(p, a, sa, c->stream)))
+      return fail(c, EDG_EHIP, std::string("source kernel: ") + hipGetErrorString((hipError_t)rc));
+    a.kind = j < L ? KIND_FUSED : KIND_NEIGHBOR;
+    if ((rc = launch_timed(c, fn, p, a, a.end))) return rc;
+    for (int l = 0; l <= lmax; ++l) c->nstep[l]++;
+    c->updates += a.end;
+    if (j < L && c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->stream)))
+      return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
+  }
+  c->level += L;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) {
+    for (size_t i = 0; i < c->ev_used; ++i) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[i].first, c->ev_pool[i].second));
+      c->t_ms += ms;
+      c->t_launches++;
+      c->t_updates += c->ev_updates[i];
+    }
+  }
+  return EDG_OK;
+}
+
+int edg_read_receivers(edg_ctx* c, int32_t run, double* out, int64_t cap) {
+  if (!c) return EDG_EINVAL;
+  if (run != 0 || !out) return fail(c, EDG_EINVAL, "bad run or null output");
+  const int64_t need = (int64_t)c->n_rec * c->rec_ns * LPE;
+  if (cap < need) return fail(c, EDG_ECAP, "output capacity too small");
+  if (need == 0) return EDG_OK;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  HIPCHK(c, hipMemcpy(out, c->r_out.p, need * sizeof(double), hipMemcpyDeviceToHost));
+  return EDG_OK;
+}
+
+double edg_time(const edg_ctx* c) { return c ? (double)c->level * c->dt_cl[0] : 0.0; }
+
+const char* edg_last_error(const edg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int edg_enable_timing(edg_ctx* c, int32_t enable) {
+  if (!c) return EDG_EINVAL;
+  c->timing = enable != 0;
+  if (c->timing) {
+    c->t_launches = 0;
+    c->t_updates = 0;
+    c->t_ms = 0;
+  }
+  return EDG_OK;
+}
+
+int edg_kernel_stats(const edg_ctx* c, int64_t* launches, double* total_ms, int64_t* upd) {
+  if (!c) return EDG_EINVAL;
+  if (launches) *launches = c->t_launches;
+  if (total_ms) *total_ms = c->t_ms;
+  if (upd) *upd = c->t_updates;
+  return EDG_OK;
+}
+
+int64_t edg_element_updates(const edg_ctx* c) { return c ? c->updates : 0; }
+
+void edg_destroy(edg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->cfg.device);
+  delete c;
+}
+
+int edg_reference_matrices(int32_t order, double* K, double* Ft) {
+  if (order < 1 || order > 8 || !K || !Ft) return EDG_EINVAL;
+  RefMats R = reference_matrices(order);
+  std::copy(R.K.begin(), R.K.end(), K);
+  std::copy(R.Ft.begin(), R.Ft.end(), Ft);
+  return EDG_OK;
+}
+
+int edg_cluster_host(int64_t K, const double* dt, const int64_t* nbr, int32_t Nc, double lam_in, int32_t* cluster,
+                     double* lam_out, double* speedup_out) {
+  if (K <= 0 || !dt || !nbr || !cluster || Nc < 1 || Nc > MAX_CLUSTERS || lam_in > 1.0) return EDG_EINVAL;
+  std::vector<int> cl;
+  double lam = 1.0, sp = 1.0;
+  cluster_all(K, dt, nbr, Nc, lam_in, cl, lam, sp);
+  for (int64_t k = 0; k < K; ++k) cluster[k] = cl[k] + 1;
+  if (lam_out) *lam_out = lam;
+  if (speedup_out) *speedup_out = sp;
+  return EDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,565 @@
+// HIP kernels (gfx950) of the ADER-DG element update with clustered rate-2
+// LTS: time kernel (Cauchy-Kowalevski), volume kernel, surface kernel with the
+// Godunov flux, anelastic relaxation, B1/B2/B3 buffer output, point sources,
+// receivers.  Sec. II-A (eqs. ader_taylor, ader_derivative_elastic,
+// ader_derivative_anelastic, volume, local/neigh surface kernels, update) and
+// Sec. IV-B (eq. lts_buffers and the buffer consumption rules).
+//
+// Work mapping.  One wave (64 lanes) owns 7 elements; lane = 9*e + q holds the
+// modal row q (0..5 stresses xx,yy,zz,xy,yz,xz; 6..8 velocities u,v,w) of
+// element e, and stress lanes also hold the m memory-variable rows of their
+// stress component.  Reference-matrix products (K_c, F~_i, F^_i) act inside a
+// row, so every lane applies the same sparse matrix: they are straight-line
+// FMAs with compile-time constants (generated/refmats.h).  Products that mix
+// rows (Jacobians, star matrices, flux solvers, anelastic coupling) go through
+// a per-wave LDS exchange.  Lane 63 is idle.
+//
+// Differences from the paper's own kernel layout (prior art for Xeon):
+//  * the star matrices are applied as "inverse Jacobian, then physical
+//    Jacobian" (same product, re-associated) from ~20 compact per-element
+//    parameters instead of stored 9x9 / 6x9 matrices;
+//  * the flux solvers are evaluated on the fly (Godunov state in the face
+//    normal frame) instead of stored 9x9 / 6x9 matrices;
+//  * every element's local vertices are sorted by global vertex id, so both
+//    sides of a face parameterise it identically and the 12 neighbour flux
+//    matrices F-_{j,h} collapse to the 4 F~_j: buffers are stored as face
+//    traces (B F~_j, 9 x F per face), produced once by their owner;
+//  * the local and neighbouring surface contributions of a step are applied
+//    together at the end of the step (one Godunov solve and one lift per face)
+//    from the element's own B1 trace and the neighbour data;
+//  * ping-pong trace slots (by step parity) let one launch per finest level
+//    finish the step of every active element and start its next one.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "generated/refmats.h"
+#include "kernels.hpp"
+
+namespace edg {
+
+namespace {
+
+constexpr int EPW = 7;   // elements per wave
+constexpr int LPE = 9;   // lanes per element
+constexpr int NSLOT = EPW * LPE;  // 63 elastic slots per mode in the tiled layout
+
+__device__ __forceinline__ int sym_index(int i, int j) {
+  // (0,0)->0 (1,1)->1 (2,2)->2 (0,1)->3 (1,2)->4 (0,2)->5
+  if (i == j) return i;
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  return a == 0 ? (b == 1 ? 3 : 5) : 4;
+}
+
+__device__ __forceinline__ int cluster_of(const LevelArgs& a, int elem) {
+  int c = 0;
+#pragma unroll
+  for (int l = 0; l < MAX_CLUSTERS - 1; ++l)
+    if (l < a.n_clusters - 1 && elem >= a.cl_end[l]) c = l + 1;
+  return c;
+}
+
+template <class R, int O, int M>
+struct LdsLayout {
+  using RF = edg_gen::Ref<O>;
+  static constexpr int B = RF::B, FP = RF::FP;
+  static constexpr int FACE = 4 * 2 * LPE * FP;           // [face][side][row][f]
+  static constexpr int GRAD = LPE * 3 * B + 3 * (M > 0 ? M : 0) * B;  // [row][dir][b] + [l][k<3][b]
+  static constexpr int REGION = FACE > GRAD ? FACE : GRAD;
+  static constexpr int TOTAL = (EPW + 1) * REGION;        // +1: scratch for the idle lane
+};
+
+// Godunov flux of one face mode: qm / qp are the 9 elastic trace coefficients
+// of this element and of the outside state; writes s * (A_n q*) for the 9
+// elastic rows and s * (strain-rate flux) for the 6 memory-variable rows
+// (unscaled by omega), where s = 2|S_i| / |det J| (the surface kernel's
+// -(1/|det J|) int_face phi ... with the sign folded in).
+template <class R>
+__device__ __forceinline__ void godunov(const R* qm, const R* qp, R nx, R ny, R nz, R zpm, R zsm, R zpp, R zsp,
+                                        R lam, R mu, R rho_inv, R s, int bc, R* out) {
+  // tractions sigma n and velocities
+  const R tmx = qm[0] * nx + qm[3] * ny + qm[5] * nz;
+  const R tmy = qm[3] * nx + qm[1] * ny + qm[4] * nz;
+  const R tmz = qm[5] * nx + qm[4] * ny + qm[2] * nz;
+  const R vmx = qm[6], vmy = qm[7], vmz = qm[8];
+  R tpx, tpy, tpz, vpx, vpy, vpz;
+  if (bc == 0) {
+    tpx = qp[0] * nx + qp[3] * ny + qp[5] * nz;
+    tpy = qp[3] * nx + qp[1] * ny + qp[4] * nz;
+    tpz = qp[5] * nx + qp[4] * ny + qp[2] * nz;
+    vpx = qp[6]; vpy = qp[7]; vpz = qp[8];
+  } else if (bc == 1) {  // free surface: mirror state (traction flips, velocity kept)
+    tpx = -tmx; tpy = -tmy; tpz = -tmz;
+    vpx = vmx; vpy = vmy; vpz = vmz;
+  } else {               // absorbing: zero outside state
+    tpx = tpy = tpz = R(0);
+    vpx = vpy = vpz = R(0);
+  }
+  const R tnm = tmx * nx + tmy * ny + tmz * nz, vnm = vmx * nx + vmy * ny + vmz * nz;
+  const R tnp = tpx * nx + tpy * ny + tpz * nz, vnp = vpx * nx + vpy * ny + vpz * nz;
+  const R ip = R(1) / (zpm + zpp), is = R(1) / (zsm + zsp);
+  const R vn = (zpm * vnm + zpp * vnp + tnp - tnm) * ip;
+  const R tn = (zpp * tnm + zpm * tnp + zpm * zpp * (vnp - vnm)) * ip;
+  // tangential parts
+  const R tTmx = tmx - tnm * nx, tTmy = tmy - tnm * ny, tTmz = tmz - tnm * nz;
+  const R vTmx = vmx - vnm * nx, vTmy = vmy - vnm * ny, vTmz = vmz - vnm * nz;
+  const R tTpx = tpx - tnp * nx, tTpy = tpy - tnp * ny, tTpz = tpz - tnp * nz;
+  const R vTpx = vpx - vnp * nx, vTpy = vpy - vnp * ny, vTpz = vpz - vnp * nz;
+  const R zz = zsm * zsp;
+  const R vx = vn * nx + (zsm * vTmx + zsp * vTpx + tTpx - tTmx) * is;
+  const R vy = vn * ny + (zsm * vTmy + zsp * vTpy + tTpy - tTmy) * is;
+  const R vz = vn * nz + (zsm * vTmz + zsp * vTpz + tTpz - tTmz) * is;
+  const R tx = tn * nx + (zsp * tTmx + zsm * tTpx + zz * (vTpx - vTmx)) * is;
+  const R ty = tn * ny + (zsp * tTmy + zsm * tTpy + zz * (vTpy - vTmy)) * is;
+  const R tz = tn * nz + (zsp * tTmz + zsm * tTpz + zz * (vTpz - vTmz)) * is;
+  // flux A_n q*: stresses -(lam (v.n) I + mu (n v^T + v n^T)), velocities -t/rho;
+  // multiplied by -s for the surface term: +s (...)
+  const R lvn = lam * vn;
+  const R ms = mu * s;
+  out[0] = s * lvn + R(2) * ms * nx * vx;
+  out[1] = s * lvn + R(2) * ms * ny * vy;
+  out[2] = s * lvn + R(2) * ms * nz * vz;
+  out[3] = ms * (nx * vy + ny * vx);
+  out[4] = ms * (ny * vz + nz * vy);
+  out[5] = ms * (nx * vz + nz * vx);
+  const R sr = s * rho_inv;
+  out[6] = sr * tx;
+  out[7] = sr * ty;
+  out[8] = sr * tz;
+  // memory-variable rows: -(1/2)(n v^T + v n^T), times -s
+  const R hs = R(0.5) * s;
+  out[9] = s * nx * vx;
+  out[10] = s * ny * vy;
+  out[11] = s * nz * vz;
+  out[12] = hs * (nx * vy + ny * vx);
+  out[13] = hs * (ny * vz + nz * vy);
+  out[14] = hs * (nx * vz + nz * vx);
+}
+
+template <class R, int O, int M>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_level(KPtrs p, LevelArgs a) {
+  using RF = edg_gen::Ref<O>;
+  using L = LdsLayout<R, O, M>;
+  constexpr int B = RF::B, F = RF::F, FP = RF::FP;
+  constexpr int MM = M > 0 ? M : 1;
+  __shared__ R lds[L::TOTAL];
+
+  const int lane = threadIdx.x;
+  const int e = lane / LPE, q = lane % LPE;
+  const int ec = e < EPW ? e : EPW - 1;
+  const int g = blockIdx.x;
+  const int elem = g * EPW + ec;
+  const bool valid = (e < EPW) && (elem < a.end);
+  const int slot_e = ec * LPE + q;           // elastic slot (lane 63 aliases 62's element)
+  const int slot_a = ec * 6 + (q < 6 ? q : 0);
+  R* const reg = lds + e * L::REGION;
+
+  R* Qe = reinterpret_cast<R*>(p.Qe);
+  R* Qa = reinterpret_cast<R*>(p.Qa);
+  const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
+  const int* FI = p.FI + (size_t)elem * 8;
+  const size_t Kp = (size_t)p.Kp;
+  const size_t tstride = (size_t)4 * LPE * FP;   // per element in a trace slot
+
+  const int cl = cluster_of(a, elem);
+  const bool is_stress = q < 6;
+  int qi = 0, qj = 0;                        // stress component (i, j)
+  if (q < 3) { qi = q; qj = q; }
+  else if (q == 3) { qi = 0; qj = 1; }
+  else if (q == 4) { qi = 1; qj = 2; }
+  else if (q == 5) { qi = 0; qj = 2; }
+  const R delta = q < 3 ? R(1) : R(0);
+
+  // element parameters
+  R G[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) G[c] = P[c];
+  const R rho_inv = P[9], lam = P[10], mu = P[11], zp = P[12], zs = P[13];
+  R al[MM], bl[MM], om[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    al[l] = M > 0 ? P[14 + 2 * l] : R(0);
+    bl[l] = M > 0 ? P[15 + 2 * l] : R(0);
+    om[l] = M > 0 ? R(a.omega[l]) : R(0);
+  }
+
+  // DOFs
+  R qe[B];
+  R qa[MM][B];
+  const size_t gbase = (size_t)g * B;
+#pragma unroll
+  for (int b = 0; b < B; ++b) qe[b] = Qe[(gbase + b) * NSLOT + slot_e];
+  if (M > 0 && is_stress) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int l = 0; l < MM; ++l) qa[l][b] = Qa[((gbase + b) * MM + l) * (EPW * 6) + slot_a];
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int l = 0; l < MM; ++l) qa[l][b] = R(0);
+  }
+
+  // ------------------------------------------------ surface: finish step n
+  if (a.kind != KIND_PREDICT) {
+    const int n = a.step_fin[cl];
+    const R* T1 = reinterpret_cast<const R*>(p.T1);
+    const R* T2 = reinterpret_cast<const R*>(p.T2);
+    const R* T3 = reinterpret_cast<const R*>(p.T3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int nb = FI[2 * i];
+      const int code = FI[2 * i + 1];
+      const int j = code & 15, rel = ((code >> 8) & 15) - 1;
+      const R* own = T1 + ((size_t)(n & 1) * Kp + elem) * tstride + (size_t)(i * LPE + q) * FP;
+      R* dm = reg + ((i * 2 + 0) * LPE + q) * FP;
+      R* dp = reg + ((i * 2 + 1) * LPE + q) * FP;
+#pragma unroll
+      for (int f = 0; f < FP; ++f) dm[f] = own[f];
+      if (nb >= 0) {
+        const size_t nbo = (size_t)nb * tstride + (size_t)(j * LPE + q) * FP;
+        if (rel == 0) {
+          const R* s = T1 + (size_t)(n & 1) * Kp * tstride + nbo;
+#pragma unroll
+          for (int f = 0; f < FP; ++f) dp[f] = s[f];
+        } else if (rel < 0) {       // finer neighbour: its accumulated B3
+          const R* s = T3 + (size_t)(n & 1) * Kp * tstride + nbo;
+#pragma unroll
+          for (int f = 0; f < FP; ++f) dp[f] = s[f];
+        } else {                    // coarser neighbour: B2, then B1 - B2
+          const int c = (n >> 1) & 1;
+          const R* s2 = T2 + (size_t)c * Kp * tstride + nbo;
+          if ((n & 1) == 0) {
+#pragma unroll
+            for (int f = 0; f < FP; ++f) dp[f] = s2[f];
+          } else {
+            const R* s1 = T1 + (size_t)c * Kp * tstride + nbo;
+#pragma unroll
+            for (int f = 0; f < FP; ++f) dp[f] = s1[f] - s2[f];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < FP; ++f) dp[f] = R(0);
+      }
+    }
+    __syncthreads();
+    // Godunov solves: 4F (face, mode) items spread over the element's 9 lanes
+#pragma unroll
+    for (int r = 0; r < (4 * F + LPE - 1) / LPE; ++r) {
+      const int t = q + LPE * r;
+      if (t < 4 * F) {
+        const int i = t / F, f = t % F;
+        const int code = FI[2 * i + 1];
+        const int bc = (code >> 4) & 15;
+        const R* fp = P + 20 + 6 * i;
+        R qm[9], qp[9], out[15];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          qm[k] = reg[((i * 2 + 0) * LPE + k) * FP + f];
+          qp[k] = reg[((i * 2 + 1) * LPE + k) * FP + f];
+        }
+        const R zpp = bc == 0 ? fp[4] : zp, zsp = bc == 0 ? fp[5] : zs;
+        godunov<R>(qm, qp, fp[0], fp[1], fp[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fp[3], bc, out);
+#pragma unroll
+        for (int k = 0; k < 15; ++k) reg[((i * 2 + k / 9) * LPE + k % 9) * FP + f] = out[k];
+      }
+    }
+    __syncthreads();
+    {
+      R pf[4 * FP];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) pf[i * FP + f] = reg[((i * 2 + 0) * LPE + q) * FP + f];
+      RF::lift(pf, qe);
+      if (M > 0 && is_stress) {
+        R da[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) da[b] = R(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int f = 0; f < FP; ++f) pf[i * FP + f] = reg[((i * 2 + 1) * LPE + q) * FP + f];
+        RF::lift(pf, da);
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int b = 0; b < B; ++b) qa[l][b] += om[l] * da[b];
+      }
+    }
+    __syncthreads();
+  }
+
+  if (a.kind == KIND_NEIGHBOR) {
+    if (valid) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) Qe[(gbase + b) * NSLOT + slot_e] = qe[b];
+      if (M > 0 && is_stress)
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+          for (int l = 0; l < MM; ++l) Qa[((gbase + b) * MM + l) * (EPW * 6) + slot_a] = qa[l][b];
+    }
+    return;
+  }
+
+  // ------------------------------------------------ time kernel: predict step nn
+  const int nn = a.step_new[cl];
+  const int eflags = p.EF[elem];
+  const int rec_slot = p.rec_slot ? p.rec_slot[elem] : -1;
+  R de[B], te[B], t2[B];
+  R dm[MM][B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) { de[b] = qe[b]; te[b] = R(0); t2[b] = R(0); }
+#pragma unroll
+  for (int l = 0; l < MM; ++l)
+#pragma unroll
+    for (int b = 0; b < B; ++b) dm[l][b] = qa[l][b];
+
+  // LDS rows: gradients grad[row][dir][b]; normal memory rows trm[l][k][b]
+  R* const grad = reg;
+  R* const trm = reg + LPE * 3 * B;
+  // rows this lane reads back
+  int rA = 0, rB = 0, rC = 0;   // velocity lane: sigma_{i,d} along d
+  if (!is_stress) {
+    const int i = q - 6;
+    rA = sym_index(i, 0) * 3 * B + 0 * B;
+    rB = sym_index(i, 1) * 3 * B + 1 * B;
+    rC = sym_index(i, 2) * 3 * B + 2 * B;
+  }
+  const int eA = (6 + qi) * 3 * B + qj * B;   // d v_i / d x_j
+  const int eB = (6 + qj) * 3 * B + qi * B;   // d v_j / d x_i
+  const int d0 = 6 * 3 * B + 0 * B, d1 = 7 * 3 * B + 1 * B, d2 = 8 * 3 * B + 2 * B;
+
+#pragma unroll 1
+  for (int d = 0; d < O; ++d) {
+    const R c = R(a.tc[cl][d]), h = R(a.th[cl][d]);
+#pragma unroll
+    for (int b = 0; b < B; ++b) { te[b] += c * de[b]; t2[b] += h * de[b]; }
+    if (rec_slot >= 0 && valid) {
+      R* rd = reinterpret_cast<R*>(p.recD) + (((size_t)rec_slot * O + d) * LPE + q) * B;
+#pragma unroll
+      for (int b = 0; b < B; ++b) rd[b] = de[b];
+    }
+    if (d + 1 < O) RF::ck_grad(de, G, grad + q * 3 * B);
+    if (M > 0 && q < 3)
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+#pragma unroll
+        for (int b = 0; b < B; ++b) trm[(l * 3 + q) * B + b] = dm[l][b];
+    __syncthreads();
+    if (is_stress) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        R coup = R(0);
+#pragma unroll
+        for (int l = 0; l < MM; ++l) {
+          if (M > 0) {
+            const R tr = trm[(l * 3 + 0) * B + b] + trm[(l * 3 + 1) * B + b] + trm[(l * 3 + 2) * B + b];
+            coup -= al[l] * delta * tr + bl[l] * dm[l][b];
+          }
+        }
+        if (M > 0) {
+          qe[b] += c * coup;                       // volume: E^l T^{a,l}
+#pragma unroll
+          for (int l = 0; l < MM; ++l) qa[l][b] -= om[l] * c * dm[l][b];   // volume: -omega_l T^{a,l}
+        }
+        if (d + 1 < O) {
+          const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+          const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+          de[b] = lam * delta * div + R(2) * mu * eps + coup;
+#pragma unroll
+          for (int l = 0; l < MM; ++l)
+            if (M > 0) dm[l][b] = om[l] * (eps - dm[l][b]);
+        }
+      }
+    } else if (d + 1 < O) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) de[b] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+    }
+    __syncthreads();
+  }
+
+  // ------------------------------------------------ buffers as face traces
+  {
+    R pt[4 * FP];
+    RF::trace(te, pt);
+    const size_t own = ((size_t)(nn & 1) * Kp + elem) * tstride + (size_t)q * FP;
+    if (valid) {
+      R* T1 = reinterpret_cast<R*>(p.T1);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) T1[own + (size_t)i * LPE * FP + f] = pt[i * FP + f];
+    }
+    if (eflags & EF_HAS_COARSER) {     // B3: restart on even steps, accumulate on odd
+      R* T3 = reinterpret_cast<R*>(p.T3);
+      const size_t o3 = ((size_t)((nn >> 1) & 1) * Kp + elem) * tstride + (size_t)q * FP;
+      if (valid) {
+        if ((nn & 1) == 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int f = 0; f < FP; ++f) T3[o3 + (size_t)i * LPE * FP + f] = pt[i * FP + f];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int f = 0; f < FP; ++f) T3[o3 + (size_t)i * LPE * FP + f] += pt[i * FP + f];
+        }
+      }
+    }
+    if (__any((eflags & EF_HAS_FINER) != 0)) {   // B2: half-step integral
+      RF::trace(t2, pt);
+      if (valid && (eflags & EF_HAS_FINER)) {
+        R* T2 = reinterpret_cast<R*>(p.T2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int f = 0; f < FP; ++f) T2[own + (size_t)i * LPE * FP + f] = pt[i * FP + f];
+      }
+    }
+  }
+
+  // ------------------------------------------------ volume kernel
+  RF::vol_grad(te, G, grad + q * 3 * B);
+  __syncthreads();
+  if (is_stress) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+      const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+      qe[b] -= lam * delta * div + R(2) * mu * eps;
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+        if (M > 0) qa[l][b] -= om[l] * eps;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) qe[b] -= rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+  }
+
+  if (valid) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) Qe[(gbase + b) * NSLOT + slot_e] = qe[b];
+    if (M > 0 && is_stress)
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int l = 0; l < MM; ++l) Qa[((gbase + b) * MM + l) * (EPW * 6) + slot_a] = qa[l][b];
+  }
+}
+
+// point sources: Q[stress] += -M phi(x_s) / |det J| * (S(t1) - S(t0)) for the
+// step of the source's element that ends at this level
+__device__ double stf_antiderivative(int kind, double p0, double p1, double t) {
+  if (kind == 0) {  // Ricker moment rate: S = (t - t0) exp(-a (t - t0)^2), a = (pi fc)^2
+    const double a = (M_PI * p0) * (M_PI * p0);
+    const double tau = t - p1;
+    return tau * exp(-a * tau * tau);
+  }
+  // Hann moment rate on [t0, t0 + T]
+  const double tau = t - p0;
+  if (tau <= 0.0) return 0.0;
+  if (tau >= p1) return 1.0;
+  return (tau - p1 / (2.0 * M_PI) * sin(2.0 * M_PI * tau / p1)) / p1;
+}
+
+template <class R, int O, int M>
+__global__ void k_sources(KPtrs p, LevelArgs a, SrcArgs s) {
+  constexpr int B = edg_gen::Ref<O>::B;
+  constexpr int MM = M > 0 ? M : 1;
+  (void)MM;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int src = t / (6 * B);
+  if (src >= s.n) return;
+  const int qb = t % (6 * B), qq = qb / B, b = qb % B;
+  const int elem = s.elem[src];
+  if (elem >= a.end) return;
+  const int cl = cluster_of(a, elem);
+  const double dt = a.dt[cl];
+  const int n = a.step_fin[cl];
+  const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
+  const double w = stf_antiderivative(s.kind[src], s.par[2 * src], s.par[2 * src + 1], t1) -
+                   stf_antiderivative(s.kind[src], s.par[2 * src], s.par[2 * src + 1], t0);
+  const double inc = -s.moment[6 * src + qq] * s.phi[(size_t)src * B + b] * s.inv_det[src] * w;
+  const int g = elem / EPW, e = elem % EPW;
+  R* Qe = reinterpret_cast<R*>(p.Qe);
+  atomicAdd(&Qe[((size_t)g * B + b) * NSLOT + e * LPE + qq], R(inc));
+}
+
+// receivers: evaluate the predicted Taylor expansion at the sample times in
+// [t^n, t^{n+1}) of every receiver whose element was predicted at this level
+template <class R, int O, int M>
+__global__ void k_receivers(KPtrs p, LevelArgs a, RecArgs r) {
+  constexpr int B = edg_gen::Ref<O>::B;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rec = t / LPE, q = t % LPE;
+  if (rec >= r.n) return;
+  const int elem = r.elem[rec];
+  if (elem >= a.end) return;
+  const int cl = cluster_of(a, elem);
+  const double dt = a.dt[cl];
+  const int n = a.step_new[cl];
+  const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
+  const R* D = reinterpret_cast<const R*>(p.recD) + (size_t)r.slot[rec] * O * LPE * B;
+  double val[O];
+  for (int d = 0; d < O; ++d) {
+    double v = 0.0;
+    for (int b = 0; b < B; ++b) v += (double)D[((size_t)d * LPE + q) * B + b] * r.phi[(size_t)rec * B + b];
+    val[d] = v;
+  }
+  long long s = (long long)floor(t0 / r.dt_sample) - 1;
+  if (s < 0) s = 0;
+  for (; s < r.ns && (double)s * r.dt_sample < t1; ++s) {
+    const double ts = (double)s * r.dt_sample;
+    if (ts < t0) continue;
+    const double x = ts - t0;
+    double acc = 0.0, pw = 1.0, fact = 1.0;
+    for (int d = 0; d < O; ++d) {
+      acc += pw / fact * val[d];
+      pw *= x;
+      fact *= (double)(d + 1);
+    }
+    r.out[((size_t)rec * r.ns + s) * LPE + q] = acc;
+  }
+}
+
+}  // namespace
+
+template <class R, int O, int M>
+int launch_level(const KPtrs& p, const LevelArgs& a, hipStream_t st) {
+  const int grid = (a.end + EPW - 1) / EPW;
+  if (grid <= 0) return 0;
+  hipLaunchKernelGGL((k_level<R, O, M>), dim3(grid), dim3(64), 0, st, p, a);
+  return (int)hipGetLastError();
+}
+
+template <class R, int O, int M>
+int launch_sources(const KPtrs& p, const LevelArgs& a, const SrcArgs& s, hipStream_t st) {
+  if (s.n <= 0) return 0;
+  constexpr int B = edg_gen::Ref<O>::B;
+  const int total = s.n * 6 * B;
+  hipLaunchKernelGGL((k_sources<R, O, M>), dim3((total + 255) / 256), dim3(256), 0, st, p, a, s);
+  return (int)hipGetLastError();
+}
+
+template <class R, int O, int M>
+int launch_receivers(const KPtrs& p, const LevelArgs& a, const RecArgs& r, hipStream_t st) {
+  if (r.n <= 0) return 0;
+  const int total = r.n * LPE;
+  hipLaunchKernelGGL((k_receivers<R, O, M>), dim3((total + 127) / 128), dim3(128), 0, st, p, a, r);
+  return (int)hipGetLastError();
+}
+
+#define EDG_INST(R, O, M)                                                                        \
+  template int launch_level<R, O, M>(const KPtrs&, const LevelArgs&, hipStream_t);              \
+  template int launch_sources<R, O, M>(const KPtrs&, const LevelArgs&, const SrcArgs&, hipStream_t); \
+  template int launch_receivers<R, O, M>(const KPtrs&, const LevelArgs&, const RecArgs&, hipStream_t);
+
+EDG_KERNEL_INSTANCES
+
+}  // namespace edg

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded inputs.  FP64 runs must agree to relative L2 <= 1e-11, FP32 runs
+to <= 2e-5 (each FP32 result's error is printed)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.solver import Oracle, plane_wave_p, project
+from tests.helpers import anelastic_setup, gpu_context, parity, random_direction_wavevector, seis_parity
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 2e-5
+
+
+def _c1(direction, kn, steps=50):
+    mesh = synth.kuhn_cube_periodic(6, 1000.0)
+    K = mesh["tet_verts"].shape[0]
+    mat = synth.homogeneous_materials(K)
+    w = dict(mesh=mesh, mat=mat)
+    orc = Oracle(mesh, mat, 3, cfl=0.5)
+    q = plane_wave_p(direction, kn, 2700.0, 6000.0, 3464.0)
+    q0 = project(mesh["tet_xyz"], 3, lambda x: q(x, 0.0))
+    orc.set_initial(q0)
+    ctx = gpu_context(w, 3, 1, True, lam=1.0, mechanisms=0)
+    ctx.set_initial(q0)
+    t = steps * orc.sync_dt
+    info = ctx.get_clusters()
+    assert info["sync_dt"] == pytest.approx(orc.sync_dt, rel=1e-14)
+    orc.run(t)
+    ctx.advance_to(t)
+    return ctx.read_dofs(), orc.Q, project(mesh["tet_xyz"], 3, lambda x: q(x, t))
+
+
+def test_c1_plane_wave_axis_fp64():
+    gpu, ref, exact = _c1([1.0, 0.0, 0.0], 2 * math.pi / 500.0)
+    e = parity(gpu, ref)
+    print(f"C1 axis FP64 parity {e:.3e}")
+    assert e <= TOL64
+    assert parity(gpu, exact) < 0.03
+
+
+def test_c1_plane_wave_seeded_direction_fp64():
+    n, kn = random_direction_wavevector(1)
+    gpu, ref, exact = _c1(n, kn)
+    e = parity(gpu, ref)
+    print(f"C1 seeded-direction FP64 parity {e:.3e}, wavelength {2 * math.pi / kn:.1f} m")
+    assert e <= TOL64
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_anelastic_lts_fp64(order):
+    w = anelastic_setup("tiny", order, 3)
+    orc = Oracle(w["mesh"], w["mat"], order, attn=w["attn"], n_clusters=3, lam=None, sources=w["src"],
+                 receivers=dict(xyz=w["rec"], dt_sample=1e-3, n_samples=200))
+    ctx = gpu_context(w, order, 3, True)
+    info = ctx.get_clusters()
+    assert np.array_equal(info["clusters"], orc.cl)
+    assert info["lam"] == orc.lam_lts and info["sync_dt"] == pytest.approx(orc.sync_dt, rel=1e-15)
+    assert len(np.unique(orc.cl)) >= 2
+    q0 = synth.random_state(5, orc.K, 27, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    ctx.set_sources(w["src"]["xyz"], w["src"]["moment"], w["src"]["stf_kind"], w["src"]["stf_params"])
+    ctx.set_receivers(w["rec"], 1e-3, 200)
+    t = 2 * orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    e = parity(ctx.read_dofs(), orc.Q)
+    es = seis_parity(ctx.read_receivers(), orc.seis)
+    print(f"anelastic LTS FP64 O={order}: dofs {e:.3e} receivers {es:.3e}")
+    assert e <= TOL64 and es <= TOL64
+
+
+@pytest.mark.parametrize("order", [3, 5])
+def test_anelastic_lts_fp32(order):
+    w = anelastic_setup("tiny", order, 3)
+    orc = Oracle(w["mesh"], w["mat"], order, attn=w["attn"], n_clusters=3, lam=None, sources=w["src"],
+                 receivers=dict(xyz=w["rec"], dt_sample=1e-3, n_samples=200))
+    ctx = gpu_context(w, order, 3, False)
+    q0 = synth.random_state(6, orc.K, 27, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    ctx.set_sources(w["src"]["xyz"], w["src"]["moment"], w["src"]["stf_kind"], w["src"]["stf_params"])
+    ctx.set_receivers(w["rec"], 1e-3, 200)
+    t = 2 * orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    e = parity(ctx.read_dofs(), orc.Q)
+    es = seis_parity(ctx.read_receivers(), orc.seis)
+    print(f"anelastic LTS FP32 O={order}: dofs {e:.3e} receivers {es:.3e}")
+    assert e <= TOL32 and es <= TOL32
+
+
+def test_elastic_lts_heterogeneous_fp64():
+    """Elastic heterogeneous periodic mesh with 3 clusters (interior faces only,
+    heterogeneous Godunov fluxes), several ragged groups."""
+    mesh = synth.kuhn_cube_periodic(3, 1000.0, jitter=0.15, seed=3)
+    K = mesh["tet_verts"].shape[0]
+    mat = synth.random_materials(K, 7)
+    w = dict(mesh=mesh, mat=mat)
+    orc = Oracle(mesh, mat, 4, n_clusters=3, lam=None)
+    ctx = gpu_context(w, 4, 3, True, mechanisms=0)
+    assert np.array_equal(ctx.get_clusters()["clusters"], orc.cl)
+    q0 = synth.random_state(8, K, 9, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    t = 3 * orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    e = parity(ctx.read_dofs(), orc.Q)
+    print(f"elastic heterogeneous LTS FP64: {e:.3e}")
+    assert e <= TOL64
+
+
+@pytest.mark.parametrize("ncube", [1, 2])
+def test_tiny_meshes_edge_cases(ncube):
+    """K = 6 (a single Kuhn cube, one partly filled group) and K = 48, all
+    boundary faces absorbing or free."""
+    mesh = synth.layered_box(ncube, ncube, [100.0] * ncube, 100.0 * ncube, 100.0 * ncube)
+    K = mesh["tet_verts"].shape[0]
+    mat = synth.random_materials(K, 2)
+    w = dict(mesh=mesh, mat=mat, attn=synth.attenuation_inputs(mat, 3, 0.1, 10.0))
+    orc = Oracle(mesh, mat, 3, attn=w["attn"], n_clusters=2, lam=None)
+    ctx = gpu_context(w, 3, 2, True)
+    q0 = synth.random_state(4, K, 27, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    t = 2 * orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    assert parity(ctx.read_dofs(), orc.Q) <= TOL64
+
+
+def test_split_advance_is_bitwise_identical():
+    w = anelastic_setup("tiny", 3, 3)
+    q0 = synth.random_state(9, w["mesh"]["tet_verts"].shape[0], 27, 10)
+    out = []
+    for split in (False, True):
+        ctx = gpu_context(w, 3, 3, False)
+        ctx.set_initial(q0)
+        ctx.set_sources(w["src"]["xyz"], w["src"]["moment"], w["src"]["stf_kind"], w["src"]["stf_params"])
+        s = ctx.get_clusters()["sync_dt"]
+        if split:
+            ctx.advance_to(s)
+            ctx.advance_to(2 * s)
+            ctx.advance_to(3 * s)
+        else:
+            ctx.advance_to(3 * s)
+        out.append(ctx.read_dofs())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_error_codes():
+    from paper_2202_10313_amd import Context, EdgError
+    w = anelastic_setup("tiny", 3, 3)
+    ctx = Context(3, mechanisms=3, n_clusters=3)
+    with pytest.raises(EdgError) as ei:
+        ctx.advance_to(1.0)
+    assert ei.value.code == -2
+    m = w["mesh"]
+    bad = m["face_bc"].copy()
+    bad[bad != 0] = 0
+    with pytest.raises(EdgError) as ei:
+        ctx.upload_mesh(m["tet_verts"], m["tet_xyz"], bad)
+    assert ei.value.code == -6
+    ctx = gpu_context(w, 3, 3, False)
+    s = ctx.get_clusters()["sync_dt"]
+    with pytest.raises(EdgError) as ei:
+        ctx.advance_to(0.5 * s)
+    assert ei.value.code == -5
+    ctx.advance_to(s)
+    with pytest.raises(EdgError):
+        ctx.set_sources(np.array([[1e9, 0, 0]]), np.ones((1, 6)), 0, np.array([[2.0, 0.75]]))
