@@ -1,0 +1,216 @@
+"""Benchmark: element updates per second of the anelastic ADER-DG LTS forward
+solve on one MI355X.
+
+Workload (synthetic, seeded): the layered 20 x 20 x 10 km box, 996,558
+jittered Kuhn tetrahedra (67 x 67 columns; 4 x 100 m, 3 x 200 m, 30 x 300 m
+layers), order 5 (35 basis functions), 3 relaxation mechanisms (27
+quantities), FP32, clustered rate-2 LTS with N_c = 3 and a searched lambda,
+free surface on top and absorbing elsewhere, layered vs 800-3500 m/s with
+vp/vs = 1.8, +-5% Gaussian perturbations, Qs = 50 vs[km/s], Qp = 2 Qs, one
+Ricker moment-tensor source (fc = 2 Hz), 64 surface receivers.
+
+One step = one LTS cycle (the coarsest cluster's time step; every element
+advances by its own steps).  The timed region is one edg_advance_to call over
+`steps` cycles, bracketed by device synchronisation; its element updates per
+second is the value.  The roofline entry uses the per-launch durations of
+the element-update kernel from HIP events recorded on the library's stream
+during the same timed region.  The CPU baseline times the FP64 oracle on a
+bounded sample (a 6 x 6-column box of the same construction, one cycle).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# FP32 FMA on the vector ALUs without packed-FP32 instructions:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# the paper's flop count per element update at O=5, m=3 when every zero of the
+# sparse matrices is skipped (Sec. VI-B, Table speedups_flops_loh3 discussion)
+PAPER_FLOPS_ALL_SPARSITY = 212688
+METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
+
+
+def face_neighbours(tet_verts):
+    """[K,4] neighbour across the face opposite each local vertex (-1 = none)."""
+    K = tet_verts.shape[0]
+    faces = []
+    for i in range(4):
+        others = [m for m in range(4) if m != i]
+        f = np.sort(tet_verts[:, others], axis=1)
+        faces.append(np.concatenate([f, np.arange(K)[:, None], np.full((K, 1), i)], axis=1))
+    F = np.concatenate(faces)
+    order = np.lexsort((F[:, 2], F[:, 1], F[:, 0]))
+    F = F[order]
+    same = np.all(F[1:, :3] == F[:-1, :3], axis=1)
+    nbr = -np.ones((K, 4), dtype=np.int64)
+    idx = np.nonzero(same)[0]
+    a, b = F[idx], F[idx + 1]
+    nbr[a[:, 3], a[:, 4]] = b[:, 3]
+    nbr[b[:, 3], b[:, 4]] = a[:, 3]
+    return nbr
+
+
+def algorithmic_bytes_per_update(cl, nbr, order, m, n_clusters, word=4):
+    """Bytes an element update must move, averaged over the updates of one
+    cycle: Q read and written once (2 Nq B), the element's own B1 written and
+    every buffer read once (ideal reuse), B2 written where a finer neighbour
+    needs it, B3 read-modify-written where a coarser one does, plus 48 words
+    of per-element parameters (inverse Jacobian, |det J|, rho/lambda/mu, the
+    anelastic weights, four faces of normal, area ratio and neighbour id)."""
+    B = order * (order + 1) * (order + 2) // 6
+    nq = 9 + 6 * m
+    ncl = np.where(nbr >= 0, cl[np.maximum(nbr, 0)], cl[:, None])
+    b2 = np.any(ncl < cl[:, None], axis=1).astype(float)
+    b3 = np.any(ncl > cl[:, None], axis=1).astype(float)
+    per = word * (2 * nq * B + 9 * B * (1 + b2 + 1.5 * b3) + 9 * B * (1 + b2 + b3)) + 4 * 48
+    weight = 2.0 ** (n_clusters - cl)           # updates per cycle of an element of cluster cl (1-based)
+    return float(np.sum(per * weight) / np.sum(weight))
+
+
+def cpu_baseline(budget_s=30.0):
+    """Oracle (FP64 NumPy) on a 6 x 6-column box of the workload's
+    construction (same spacing, layering and material recipe), one LTS cycle."""
+    from oracle.solver import Oracle
+    dz = [100.0] * 4 + [200.0] * 3 + [300.0] * 30
+    h = 20000.0 / 67
+    n = 6
+    mesh = synth.layered_box(n, n, dz, n * h, n * h, jitter=0.15, seed=20)
+    mat = synth.layered_materials(mesh, 21)
+    attn = synth.attenuation_inputs(mat, 3, 0.1, 10.0)
+    orc = Oracle(mesh, mat, 5, attn=attn, n_clusters=3, lam=None)
+    orc.set_initial(synth.random_state(1, orc.K, 27, orc.B))
+    c0, t0 = time.process_time(), time.perf_counter()
+    orc.run(orc.sync_dt)
+    t1, c1 = time.perf_counter(), time.process_time()
+    return {"value": orc.updates / (t1 - t0), "unit": "elem-updates/s", "cores": max(1, round((c1 - c0) / (t1 - t0))),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {orc.K}-tet 6x6-column box of the same construction, O=5, m=3, N_c=3, "
+                      f"one LTS cycle ({orc.updates} element updates in {t1 - t0:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--order", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2202_10313_amd import Context, STF_RICKER
+
+    print("[bench] generating the workload", file=sys.stderr, flush=True)
+    mesh = synth.loh_like_box("full", seed=20)
+    K = mesh["tet_verts"].shape[0]
+    mat = synth.layered_materials(mesh, 21)
+    attn = synth.attenuation_inputs(mat, 3, 0.1, 10.0)
+    src = synth.ricker_sources(22, 1, ((5000.0, 15000.0), (5000.0, 15000.0)), (1000.0, 5000.0), fc_range=(2.0, 2.0))
+    rec = synth.surface_receivers(23, 64, ((1000.0, 19000.0), (1000.0, 19000.0)))
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = Context(args.order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream)
+    print("[bench] uploading", file=sys.stderr, flush=True)
+    ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+    ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+    ctx.upload_clusters(None)
+    info = ctx.get_clusters()
+    sync = info["sync_dt"]
+    ctx.set_sources(src["xyz"], src["moment"], STF_RICKER, src["stf_params"])
+    total_t = (args.warmup + args.steps) * sync
+    ctx.set_receivers(rec, 0.005, int(total_t / 0.005) + 2)
+
+    print(f"[bench] warmup {args.warmup} cycles", file=sys.stderr, flush=True)
+    ctx.advance_to(args.warmup * sync)
+    u0 = ctx.element_updates()
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance_to((args.warmup + args.steps) * sync)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    updates = ctx.element_updates() - u0
+    ks = ctx.kernel_stats()
+    wall = t1 - t0
+    value = updates / wall
+    print(f"[bench] timed {args.steps} cycles: {wall * 1e3:.1f} ms, {updates} element updates", file=sys.stderr, flush=True)
+    seis = ctx.read_receivers()
+    if not np.all(np.isfinite(seis)):
+        raise RuntimeError("non-finite seismograms")
+
+    cl = info["clusters"].astype(np.int64)
+    nbr = face_neighbours(mesh["tet_verts"])
+    bpu = algorithmic_bytes_per_update(cl, nbr, args.order, 3, 3)
+    kern_s = ks["total_ms"] / 1e3
+    per_launch_ms = ks["total_ms"] / max(ks["launches"], 1)
+    upd_per_launch = ks["element_updates"] / max(ks["launches"], 1)
+    achieved_gbs = ks["element_updates"] * bpu / kern_s / 1e9
+    achieved_tf = ks["element_updates"] * PAPER_FLOPS_ALL_SPARSITY / kern_s / 1e12
+    frac_hbm = achieved_gbs / HBM_PEAK_GBS
+    frac_alu = achieved_tf / VALU_FP32_PEAK_TFLOPS
+    counts = np.bincount(cl, minlength=4)[1:]
+    roofline = {
+        "bound": "hbm" if frac_hbm >= frac_alu else "alu",
+        "achieved": achieved_gbs if frac_hbm >= frac_alu else achieved_tf,
+        "peak": HBM_PEAK_GBS if frac_hbm >= frac_alu else VALU_FP32_PEAK_TFLOPS,
+        "unit": "GB/s" if frac_hbm >= frac_alu else "TFLOP/s",
+        "frac": max(frac_hbm, frac_alu),
+        "traffic": None,
+        "kernel": "k_level<float,5,3>",
+        "launches": ks["launches"],
+        "avg_launch_ms": per_launch_ms,
+        "element_updates_per_launch": upd_per_launch,
+        "algorithmic_bytes_per_update": bpu,
+        "hbm": {"achieved_GBs": achieved_gbs, "peak_GBs": HBM_PEAK_GBS, "frac": frac_hbm},
+        "alu": {"achieved_TFLOPs": achieved_tf, "peak_TFLOPs": VALU_FP32_PEAK_TFLOPS, "frac": frac_alu,
+                "flops_per_update": PAPER_FLOPS_ALL_SPARSITY},
+    }
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "elem-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"anelastic LTS forward: layered 20x20x10 km box, {K} tets, O={args.order}, m=3, "
+                        f"N_c=3, FP32, 1 Ricker source, 64 receivers; step = one LTS cycle",
+            "tets": K, "order": args.order, "mechanisms": 3, "n_clusters": 3,
+            "lambda": info["lam"], "cluster_sizes": counts.tolist(),
+            "theoretical_lts_speedup": info["speedup"],
+            "gts_equivalent_rate": K * (args.steps * sync / info["dt_min"]) / wall,
+            "plain_only": "fused (16-run) and fwd+adjoint forms are not built",
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -188,18 +188,16 @@ def qfit(Q: np.ndarray, omega: np.ndarray, f_min: float, f_max: float) -> np.nda
     relaxation frequencies omega approximates the frequency-independent quality
     factor Q over [f_min, f_max]:
         1/Q ~= sum_l Y_l (omega_l w + omega_l^2 / Q) / (omega_l^2 + w^2)
-    sampled at 2m-1 log-spaced angular frequencies w."""
+    sampled at 2m-1 log-spaced angular frequencies w (normal equations, one
+    small system per element, solved in a batch)."""
     Q = np.asarray(Q, dtype=np.float64)
-    m = len(omega)
-    w = 2 * math.pi * np.exp(np.linspace(math.log(f_min), math.log(f_max), 2 * m - 1))
-    Y = np.empty((Q.shape[0], m))
-    uq, inv = np.unique(Q, return_inverse=True)
-    for u_idx, q in enumerate(uq):
-        A = (omega[None, :] * w[:, None] + omega[None, :] ** 2 / q) / (omega[None, :] ** 2 + w[:, None] ** 2)
-        b = np.full(w.shape, 1.0 / q)
-        y, *_ = np.linalg.lstsq(A, b, rcond=None)
-        Y[inv == u_idx] = y
-    return Y
+    w = 2 * math.pi * np.exp(np.linspace(math.log(f_min), math.log(f_max), 2 * len(omega) - 1))
+    om = omega[None, None, :]
+    A = (om * w[None, :, None] + om ** 2 / Q[:, None, None]) / (om ** 2 + w[None, :, None] ** 2)  # [K,n,m]
+    b = np.broadcast_to((1.0 / Q)[:, None], (Q.shape[0], w.shape[0]))
+    AtA = np.einsum("knl,knj->klj", A, A)
+    Atb = np.einsum("knl,kn->kl", A, b)
+    return np.linalg.solve(AtA, Atb[..., None])[..., 0]
 
 
 def attenuation_inputs(mat: dict, m: int, f_min: float, f_max: float) -> dict:
