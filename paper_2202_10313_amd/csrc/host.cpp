@@ -273,19 +273,26 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
   }
 }
 
-// DOF layout: elastic [G][B][63] (slot 9e+q), memory [G][B][m][42] (slot 6e+q)
+// DOF layout: elastic rows [G][B][63] at slot 9e+q (the lane of row q of
+// element e); memory variables [G][JB][m][6][63] with mode b = r + 9 jb at
+// slot 9e+r (the lane that owns mode b), JB = ceil(B/9)
+inline int jb_count(const edg_ctx* c) { return (c->B + LPE - 1) / LPE; }
 inline size_t qe_index(const edg_ctx* c, int64_t ki, int q, int b) {
   return ((size_t)(ki / EPW) * c->B + b) * (EPW * LPE) + (ki % EPW) * LPE + q;
 }
-inline size_t qa_index(const edg_ctx* c, int64_t ki, int l, int q, int b) {
-  return (((size_t)(ki / EPW) * c->B + b) * c->M + l) * (EPW * 6) + (ki % EPW) * 6 + q;
+inline size_t qa_index(const edg_ctx* c, int64_t ki, int l, int comp, int b) {
+  const int jb = b / LPE, r = b % LPE;
+  return ((((size_t)(ki / EPW) * jb_count(c) + jb) * c->M + l) * 6 + comp) * (EPW * LPE) + (ki % EPW) * LPE + r;
+}
+inline size_t qa_size(const edg_ctx* c) {
+  return c->M > 0 ? (size_t)c->G * jb_count(c) * c->M * 6 * EPW * LPE : 1;
 }
 
 template <class R>
 int set_dofs_t(edg_ctx* c, const double* dofs) {
   const int B = c->B, NQ = c->NQ;
   std::vector<R> he((size_t)c->G * B * EPW * LPE, R(0));
-  std::vector<R> ha(c->M > 0 ? (size_t)c->G * B * c->M * EPW * 6 : 1, R(0));
+  std::vector<R> ha(qa_size(c), R(0));
   std::vector<double> row(B);
   for (int64_t k = 0; k < c->K; ++k) {
     const int64_t ki = c->user_to_internal[k];
@@ -312,7 +319,7 @@ template <class R>
 int get_dofs_t(edg_ctx* c, double* out) {
   const int B = c->B, NQ = c->NQ;
   std::vector<R> he((size_t)c->G * B * EPW * LPE);
-  std::vector<R> ha(c->M > 0 ? (size_t)c->G * B * c->M * EPW * 6 : 1);
+  std::vector<R> ha(qa_size(c));
   HIPCHK(c, hipMemcpy(he.data(), c->Qe.p, he.size() * sizeof(R), hipMemcpyDeviceToHost));
   if (c->M > 0) HIPCHK(c, hipMemcpy(ha.data(), c->Qa.p, ha.size() * sizeof(R), hipMemcpyDeviceToHost));
   std::vector<double> row(B);
@@ -674,7 +681,7 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
   int rc;
   if ((rc = dev_alloc(c, c->Qe, (size_t)c->G * c->B * EPW * LPE * rs))) return rc;
-  if ((rc = dev_alloc(c, c->Qa, c->M > 0 ? (size_t)c->G * c->B * c->M * EPW * 6 * rs : 16))) return rc;
+  if ((rc = dev_alloc(c, c->Qa, qa_size(c) * rs))) return rc;
   const size_t tb = (size_t)2 * c->Kp * 4 * LPE * c->FP * rs;
   if ((rc = dev_alloc(c, c->T1, tb))) return rc;
   if ((rc = dev_alloc(c, c->T2, tb))) return rc;

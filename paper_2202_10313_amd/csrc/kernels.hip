@@ -7,12 +7,14 @@
 //
 // Work mapping.  One wave (64 lanes) owns 7 elements; lane = 9*e + q holds the
 // modal row q (0..5 stresses xx,yy,zz,xy,yz,xz; 6..8 velocities u,v,w) of
-// element e, and stress lanes also hold the m memory-variable rows of their
-// stress component.  Reference-matrix products (K_c, F~_i, F^_i) act inside a
-// row, so every lane applies the same sparse matrix: they are straight-line
-// FMAs with compile-time constants (generated/refmats.h).  Products that mix
-// rows (Jacobians, star matrices, flux solvers, anelastic coupling) go through
-// a per-wave LDS exchange.  Lane 63 is idle.
+// element e, and all 6m memory variables of the modes b = q + 9 jb (the
+// anelastic terms act mode by mode, so this spreads them evenly over the 9
+// lanes and keeps each mechanism's trace inside one lane).  Reference-matrix
+// products (K_c, F~_i, F^_i) act inside a row, so every lane applies the same
+// sparse matrix: they are straight-line FMAs with compile-time constants
+// (generated/refmats.h).  Products that mix rows (Jacobians, star matrices,
+// flux solvers, anelastic coupling) go through a per-wave LDS exchange.
+// Lane 63 repeats lane 54's work and never writes global memory.
 //
 // Differences from the paper's own kernel layout (prior art for Xeon):
 //  * the star matrices are applied as "inverse Jacobian, then physical
@@ -63,10 +65,11 @@ template <class R, int O, int M>
 struct LdsLayout {
   using RF = edg_gen::Ref<O>;
   static constexpr int B = RF::B, FP = RF::FP;
-  static constexpr int FACE = 4 * 2 * LPE * FP;           // [face][side][row][f]
-  static constexpr int GRAD = LPE * 3 * B + 3 * (M > 0 ? M : 0) * B;  // [row][dir][b] + [l][k<3][b]
-  static constexpr int REGION = FACE > GRAD ? FACE : GRAD;
-  static constexpr int TOTAL = (EPW + 1) * REGION;        // +1: scratch for the idle lane
+  static constexpr int FACE = 4 * 2 * LPE * FP;          // [face][side][row][f]
+  static constexpr int GRAD = LPE * 3 * B;                // [row][dir][b]
+  static constexpr int COUP = M > 0 ? 6 * B : 0;          // [stress comp][b]
+  static constexpr int REGION = FACE > GRAD + COUP ? FACE : GRAD + COUP;
+  static constexpr int TOTAL = EPW * REGION;              // lane 63 shares element 6's region
 };
 
 // Godunov flux of one face mode: qm / qp are the 9 elastic trace coefficients
@@ -143,17 +146,18 @@ void k_level(KPtrs p, LevelArgs a) {
   using L = LdsLayout<R, O, M>;
   constexpr int B = RF::B, F = RF::F, FP = RF::FP;
   constexpr int MM = M > 0 ? M : 1;
+  constexpr int JB = (B + LPE - 1) / LPE;   // modes owned per lane for the memory variables
   __shared__ R lds[L::TOTAL];
 
   const int lane = threadIdx.x;
-  const int e = lane / LPE, q = lane % LPE;
-  const int ec = e < EPW ? e : EPW - 1;
+  const int e = lane / LPE, r = lane % LPE;
+  const int ec = e < EPW ? e : EPW - 1;     // lane 63 duplicates lane 54 (same element, same row)
+  const int q = e < EPW ? r : 0;
   const int g = blockIdx.x;
   const int elem = g * EPW + ec;
   const bool valid = (e < EPW) && (elem < a.end);
-  const int slot_e = ec * LPE + q;           // elastic slot (lane 63 aliases 62's element)
-  const int slot_a = ec * 6 + (q < 6 ? q : 0);
-  R* const reg = lds + e * L::REGION;
+  const int slot = ec * LPE + q;
+  R* const reg = lds + ec * L::REGION;
 
   R* Qe = reinterpret_cast<R*>(p.Qe);
   R* Qa = reinterpret_cast<R*>(p.Qa);
@@ -164,7 +168,7 @@ void k_level(KPtrs p, LevelArgs a) {
 
   const int cl = cluster_of(a, elem);
   const bool is_stress = q < 6;
-  int qi = 0, qj = 0;                        // stress component (i, j)
+  int qi = 0, qj = 0;                        // stress component (i, j) of this row
   if (q < 3) { qi = q; qj = q; }
   else if (q == 3) { qi = 0; qj = 1; }
   else if (q == 4) { qi = 1; qj = 2; }
@@ -184,25 +188,31 @@ void k_level(KPtrs p, LevelArgs a) {
     om[l] = M > 0 ? R(a.omega[l]) : R(0);
   }
 
-  // DOFs
+  // elastic DOFs: this lane's row, all modes.  Memory variables: all
+  // 6m components of the modes b = q + 9 jb owned by this lane.
   R qe[B];
-  R qa[MM][B];
   const size_t gbase = (size_t)g * B;
 #pragma unroll
-  for (int b = 0; b < B; ++b) qe[b] = Qe[(gbase + b) * NSLOT + slot_e];
-  if (M > 0 && is_stress) {
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-#pragma unroll
-      for (int l = 0; l < MM; ++l) qa[l][b] = Qa[((gbase + b) * MM + l) * (EPW * 6) + slot_a];
-  } else {
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-#pragma unroll
-      for (int l = 0; l < MM; ++l) qa[l][b] = R(0);
+  for (int b = 0; b < B; ++b) qe[b] = Qe[(gbase + b) * NSLOT + slot];
+
+  // rows of the gradient exchange this lane reads
+  int rA = 0, rB = 0, rC = 0;   // velocity lane: sigma_{i,d} along d
+  if (!is_stress) {
+    const int i = q - 6;
+    rA = sym_index(i, 0) * 3 * B + 0 * B;
+    rB = sym_index(i, 1) * 3 * B + 1 * B;
+    rC = sym_index(i, 2) * 3 * B + 2 * B;
   }
+  const int eA = (6 + qi) * 3 * B + qj * B;   // d v_i / d x_j
+  const int eB = (6 + qj) * 3 * B + qi * B;   // d v_j / d x_i
+  const int d0 = 6 * 3 * B + 0 * B, d1 = 7 * 3 * B + 1 * B, d2 = 8 * 3 * B + 2 * B;
+  R* const grad = reg;
+  R* const coup = reg + L::GRAD;
 
   // ------------------------------------------------ surface: finish step n
+  // (the memory variables are loaded afterwards; their surface term goes
+  // through the LDS area `coup`)
+  bool coup_pending = false;
   if (a.kind != KIND_PREDICT) {
     const int n = a.step_fin[cl];
     const R* T1 = reinterpret_cast<const R*>(p.T1);
@@ -214,42 +224,42 @@ void k_level(KPtrs p, LevelArgs a) {
       const int code = FI[2 * i + 1];
       const int j = code & 15, rel = ((code >> 8) & 15) - 1;
       const R* own = T1 + ((size_t)(n & 1) * Kp + elem) * tstride + (size_t)(i * LPE + q) * FP;
-      R* dm = reg + ((i * 2 + 0) * LPE + q) * FP;
-      R* dp = reg + ((i * 2 + 1) * LPE + q) * FP;
+      R* dmn = reg + ((i * 2 + 0) * LPE + q) * FP;
+      R* dpl = reg + ((i * 2 + 1) * LPE + q) * FP;
 #pragma unroll
-      for (int f = 0; f < FP; ++f) dm[f] = own[f];
+      for (int f = 0; f < FP; ++f) dmn[f] = own[f];
       if (nb >= 0) {
         const size_t nbo = (size_t)nb * tstride + (size_t)(j * LPE + q) * FP;
         if (rel == 0) {
           const R* s = T1 + (size_t)(n & 1) * Kp * tstride + nbo;
 #pragma unroll
-          for (int f = 0; f < FP; ++f) dp[f] = s[f];
+          for (int f = 0; f < FP; ++f) dpl[f] = s[f];
         } else if (rel < 0) {       // finer neighbour: its accumulated B3
           const R* s = T3 + (size_t)(n & 1) * Kp * tstride + nbo;
 #pragma unroll
-          for (int f = 0; f < FP; ++f) dp[f] = s[f];
+          for (int f = 0; f < FP; ++f) dpl[f] = s[f];
         } else {                    // coarser neighbour: B2, then B1 - B2
           const int c = (n >> 1) & 1;
           const R* s2 = T2 + (size_t)c * Kp * tstride + nbo;
           if ((n & 1) == 0) {
 #pragma unroll
-            for (int f = 0; f < FP; ++f) dp[f] = s2[f];
+            for (int f = 0; f < FP; ++f) dpl[f] = s2[f];
           } else {
             const R* s1 = T1 + (size_t)c * Kp * tstride + nbo;
 #pragma unroll
-            for (int f = 0; f < FP; ++f) dp[f] = s1[f] - s2[f];
+            for (int f = 0; f < FP; ++f) dpl[f] = s1[f] - s2[f];
           }
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < FP; ++f) dp[f] = R(0);
+        for (int f = 0; f < FP; ++f) dpl[f] = R(0);
       }
     }
     __syncthreads();
     // Godunov solves: 4F (face, mode) items spread over the element's 9 lanes
-#pragma unroll
-    for (int r = 0; r < (4 * F + LPE - 1) / LPE; ++r) {
-      const int t = q + LPE * r;
+#pragma unroll 1
+    for (int rr = 0; rr < (4 * F + LPE - 1) / LPE; ++rr) {
+      const int t = q + LPE * rr;
       if (t < 4 * F) {
         const int i = t / F, f = t % F;
         const int code = FI[2 * i + 1];
@@ -268,6 +278,7 @@ void k_level(KPtrs p, LevelArgs a) {
       }
     }
     __syncthreads();
+    R da[B];
     {
       R pf[4 * FP];
 #pragma unroll
@@ -275,33 +286,55 @@ void k_level(KPtrs p, LevelArgs a) {
 #pragma unroll
         for (int f = 0; f < FP; ++f) pf[i * FP + f] = reg[((i * 2 + 0) * LPE + q) * FP + f];
       RF::lift(pf, qe);
-      if (M > 0 && is_stress) {
-        R da[B];
+      if (M > 0) {
 #pragma unroll
         for (int b = 0; b < B; ++b) da[b] = R(0);
+        if (is_stress) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) pf[i * FP + f] = reg[((i * 2 + 1) * LPE + q) * FP + f];
-        RF::lift(pf, da);
-#pragma unroll
-        for (int l = 0; l < MM; ++l)
-#pragma unroll
-          for (int b = 0; b < B; ++b) qa[l][b] += om[l] * da[b];
+            for (int f = 0; f < FP; ++f) pf[i * FP + f] = reg[((i * 2 + 1) * LPE + q) * FP + f];
+          RF::lift(pf, da);
+        }
       }
+    }
+    if (M > 0) {
+      // the strain-rate flux of stress component q, lifted, reaches the
+      // memory variables of that component through the mode owners
+      __syncthreads();
+      if (is_stress && e < EPW)
+#pragma unroll
+        for (int b = 0; b < B; ++b) coup[q * B + b] = da[b];
+      coup_pending = true;
     }
     __syncthreads();
   }
 
+  R qa[JB][MM][6];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) {
+    const int b = q + LPE * jb;
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        qa[jb][l][c] = M > 0 ? Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+        if (M > 0 && coup_pending && b < B) qa[jb][l][c] += om[l] * coup[c * B + b];
+      }
+  }
+  if (M > 0 && coup_pending) __syncthreads();
+
   if (a.kind == KIND_NEIGHBOR) {
     if (valid) {
 #pragma unroll
-      for (int b = 0; b < B; ++b) Qe[(gbase + b) * NSLOT + slot_e] = qe[b];
-      if (M > 0 && is_stress)
+      for (int b = 0; b < B; ++b) Qe[(gbase + b) * NSLOT + slot] = qe[b];
+      if (M > 0)
 #pragma unroll
-        for (int b = 0; b < B; ++b)
+        for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-          for (int l = 0; l < MM; ++l) Qa[((gbase + b) * MM + l) * (EPW * 6) + slot_a] = qa[l][b];
+          for (int l = 0; l < MM; ++l)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = qa[jb][l][c];
     }
     return;
   }
@@ -309,74 +342,83 @@ void k_level(KPtrs p, LevelArgs a) {
   // ------------------------------------------------ time kernel: predict step nn
   const int nn = a.step_new[cl];
   const int eflags = p.EF[elem];
+  const bool need_b2 = __any((eflags & EF_HAS_FINER) != 0);
   const int rec_slot = p.rec_slot ? p.rec_slot[elem] : -1;
   R de[B], te[B], t2[B];
-  R dm[MM][B];
+  R dm[JB][MM][6];
 #pragma unroll
   for (int b = 0; b < B; ++b) { de[b] = qe[b]; te[b] = R(0); t2[b] = R(0); }
 #pragma unroll
-  for (int l = 0; l < MM; ++l)
+  for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-    for (int b = 0; b < B; ++b) dm[l][b] = qa[l][b];
-
-  // LDS rows: gradients grad[row][dir][b]; normal memory rows trm[l][k][b]
-  R* const grad = reg;
-  R* const trm = reg + LPE * 3 * B;
-  // rows this lane reads back
-  int rA = 0, rB = 0, rC = 0;   // velocity lane: sigma_{i,d} along d
-  if (!is_stress) {
-    const int i = q - 6;
-    rA = sym_index(i, 0) * 3 * B + 0 * B;
-    rB = sym_index(i, 1) * 3 * B + 1 * B;
-    rC = sym_index(i, 2) * 3 * B + 2 * B;
-  }
-  const int eA = (6 + qi) * 3 * B + qj * B;   // d v_i / d x_j
-  const int eB = (6 + qj) * 3 * B + qi * B;   // d v_j / d x_i
-  const int d0 = 6 * 3 * B + 0 * B, d1 = 7 * 3 * B + 1 * B, d2 = 8 * 3 * B + 2 * B;
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) dm[jb][l][c] = qa[jb][l][c];
 
 #pragma unroll 1
   for (int d = 0; d < O; ++d) {
-    const R c = R(a.tc[cl][d]), h = R(a.th[cl][d]);
+    const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
+    const bool more = d + 1 < O;
 #pragma unroll
-    for (int b = 0; b < B; ++b) { te[b] += c * de[b]; t2[b] += h * de[b]; }
+    for (int b = 0; b < B; ++b) te[b] += c_d * de[b];
+    if (need_b2)
+#pragma unroll
+      for (int b = 0; b < B; ++b) t2[b] += h_d * de[b];
     if (rec_slot >= 0 && valid) {
       R* rd = reinterpret_cast<R*>(p.recD) + (((size_t)rec_slot * O + d) * LPE + q) * B;
 #pragma unroll
       for (int b = 0; b < B; ++b) rd[b] = de[b];
     }
-    if (d + 1 < O) RF::ck_grad(de, G, grad + q * 3 * B);
-    if (M > 0 && q < 3)
-#pragma unroll
-      for (int l = 0; l < MM; ++l)
-#pragma unroll
-        for (int b = 0; b < B; ++b) trm[(l * 3 + q) * B + b] = dm[l][b];
+    if (more) RF::ck_grad(de, G, grad + q * 3 * B);
     __syncthreads();
+    if (M > 0) {
+      // memory variables of the owned modes: coupling into the stresses
+      // (-sum_l a_l tr(theta^l) I + b_l theta^l), the volume term
+      // -omega_l T^{a,l}, and the next derivative omega_l (eps - theta^l)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int b = q + LPE * jb;
+        if (b < B) {
+          R eps[6];
+          if (more) {
+            eps[0] = grad[6 * 3 * B + 0 * B + b];
+            eps[1] = grad[7 * 3 * B + 1 * B + b];
+            eps[2] = grad[8 * 3 * B + 2 * B + b];
+            eps[3] = R(0.5) * (grad[6 * 3 * B + 1 * B + b] + grad[7 * 3 * B + 0 * B + b]);
+            eps[4] = R(0.5) * (grad[7 * 3 * B + 2 * B + b] + grad[8 * 3 * B + 1 * B + b]);
+            eps[5] = R(0.5) * (grad[6 * 3 * B + 2 * B + b] + grad[8 * 3 * B + 0 * B + b]);
+          }
+          R cp[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+          for (int l = 0; l < MM; ++l) {
+            const R tr = dm[jb][l][0] + dm[jb][l][1] + dm[jb][l][2];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) cp[c] -= bl[l] * dm[jb][l][c] + (c < 3 ? al[l] * tr : R(0));
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              qa[jb][l][c] -= om[l] * c_d * dm[jb][l][c];
+              if (more) dm[jb][l][c] = om[l] * (eps[c] - dm[jb][l][c]);
+            }
+          }
+          if (e < EPW)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) coup[c * B + b] = cp[c];
+        }
+      }
+      __syncthreads();
+    }
     if (is_stress) {
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        R coup = R(0);
-#pragma unroll
-        for (int l = 0; l < MM; ++l) {
-          if (M > 0) {
-            const R tr = trm[(l * 3 + 0) * B + b] + trm[(l * 3 + 1) * B + b] + trm[(l * 3 + 2) * B + b];
-            coup -= al[l] * delta * tr + bl[l] * dm[l][b];
-          }
-        }
-        if (M > 0) {
-          qe[b] += c * coup;                       // volume: E^l T^{a,l}
-#pragma unroll
-          for (int l = 0; l < MM; ++l) qa[l][b] -= om[l] * c * dm[l][b];   // volume: -omega_l T^{a,l}
-        }
-        if (d + 1 < O) {
+        const R cq = M > 0 ? coup[q * B + b] : R(0);
+        if (M > 0) qe[b] += c_d * cq;                 // volume: E^l T^{a,l}
+        if (more) {
           const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
           const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
-          de[b] = lam * delta * div + R(2) * mu * eps + coup;
-#pragma unroll
-          for (int l = 0; l < MM; ++l)
-            if (M > 0) dm[l][b] = om[l] * (eps - dm[l][b]);
+          de[b] = lam * delta * div + R(2) * mu * eps + cq;
         }
       }
-    } else if (d + 1 < O) {
+    } else if (more) {
 #pragma unroll
       for (int b = 0; b < B; ++b) de[b] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
     }
@@ -412,7 +454,7 @@ void k_level(KPtrs p, LevelArgs a) {
         }
       }
     }
-    if (__any((eflags & EF_HAS_FINER) != 0)) {   // B2: half-step integral
+    if (need_b2) {                      // B2: half-step integral
       RF::trace(t2, pt);
       if (valid && (eflags & EF_HAS_FINER)) {
         R* T2 = reinterpret_cast<R*>(p.T2);
@@ -427,15 +469,31 @@ void k_level(KPtrs p, LevelArgs a) {
   // ------------------------------------------------ volume kernel
   RF::vol_grad(te, G, grad + q * 3 * B);
   __syncthreads();
+  if (M > 0) {
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+      const int b = q + LPE * jb;
+      if (b < B) {
+        R eps[6];
+        eps[0] = grad[6 * 3 * B + 0 * B + b];
+        eps[1] = grad[7 * 3 * B + 1 * B + b];
+        eps[2] = grad[8 * 3 * B + 2 * B + b];
+        eps[3] = R(0.5) * (grad[6 * 3 * B + 1 * B + b] + grad[7 * 3 * B + 0 * B + b]);
+        eps[4] = R(0.5) * (grad[7 * 3 * B + 2 * B + b] + grad[8 * 3 * B + 1 * B + b]);
+        eps[5] = R(0.5) * (grad[6 * 3 * B + 2 * B + b] + grad[8 * 3 * B + 0 * B + b]);
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) qa[jb][l][c] -= om[l] * eps[c];
+      }
+    }
+  }
   if (is_stress) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
       const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
       qe[b] -= lam * delta * div + R(2) * mu * eps;
-#pragma unroll
-      for (int l = 0; l < MM; ++l)
-        if (M > 0) qa[l][b] -= om[l] * eps;
     }
   } else {
 #pragma unroll
@@ -444,12 +502,14 @@ void k_level(KPtrs p, LevelArgs a) {
 
   if (valid) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) Qe[(gbase + b) * NSLOT + slot_e] = qe[b];
-    if (M > 0 && is_stress)
+    for (int b = 0; b < B; ++b) Qe[(gbase + b) * NSLOT + slot] = qe[b];
+    if (M > 0)
 #pragma unroll
-      for (int b = 0; b < B; ++b)
+      for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-        for (int l = 0; l < MM; ++l) Qa[((gbase + b) * MM + l) * (EPW * 6) + slot_a] = qa[l][b];
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = qa[jb][l][c];
   }
 }
 
