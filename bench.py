@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of 2 GiB (profiler calibration of FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -115,6 +117,17 @@ def main():
 
     import torch
     from paper_2202_10313_amd import Context, STF_RICKER
+
+    if args.copy_calibration:
+        n = 1 << 29                                   # 2 GiB of float32
+        a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 3}))
+        return
 
     print("[bench] generating the workload", file=sys.stderr, flush=True)
     mesh = synth.loh_like_box("full", seed=20)
