@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libedge_lts.so")
+LIB_PATH = os.environ.get("EDG_LIBRARY") or os.path.join(HERE, "lib", "libedge_lts.so")
 
 EDG_OK = 0
 ERRORS = {-1: "EDG_EINVAL", -2: "EDG_ESTATE", -3: "EDG_ENOMEM", -4: "EDG_EHIP",

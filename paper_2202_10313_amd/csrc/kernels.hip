@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "generated/refmats.h"
 #include "kernels.hpp"
@@ -513,6 +514,488 @@ void k_level(KPtrs p, LevelArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-wave variant (O = 4, 5, FP32): a workgroup of two waves owns 7
+// elements.  Lane (e, q) of wave w keeps row q of element e for the modes
+// [MB_w, MB_w+1) only (elementwise state halves, no register spill, two
+// workgroups per SIMD); the reference-matrix products that need a whole row
+// read it from the LDS row exchange RX, and their outputs are split between
+// the waves (stiffness outputs balanced by non-zero count, two faces each for
+// the traces, the wave's own modes for the lift).  The gradient exchange
+// holds only the 18 (row, direction) pairs that are read: all three
+// directions of the velocities, d_i sigma_ij of each stress row.
+template <class R, int O, int M>
+struct Lds2 {
+  // Bank-conflict-free strides: with a row stride RS and an element stride
+  // ES = 9 RS (mod 32), lane 9e+q addresses bank RS (9e + q) (mod 32), a
+  // bijection for odd RS over the 63 working lanes.
+  using RF = edg_gen::Ref<O>;
+  static constexpr int B = RF::B, FP = RF::FP;
+  static constexpr int up(int v, int m, int r) { return v + ((r - v % m) % m + m) % m; }
+  static constexpr int BS = B % 2 ? B : B + 1;                 // row stride of mode rows (odd)
+  static constexpr int FS = FP + 1;                            // row stride of face rows (odd)
+  static constexpr int GRAD = 19 * BS;          // 18 used (row, dir) pairs + 1 dummy row
+  static constexpr int COUP = 6 * BS;
+  static constexpr int RX = LPE * BS;
+  static constexpr int REST = GRAD + COUP + RX;
+  static constexpr int REGION = up(REST, 32, (9 * BS) % 32);   // element stride of the mode areas
+  static constexpr int FACE = up(4 * 2 * LPE * FS, 32, (9 * FS) % 32);  // element stride of the face area
+  static constexpr int TOTAL = EPW * (REGION > FACE ? REGION : FACE);
+};
+
+// An opaque copy of a lane index: addresses built from it are recomputed at
+// the point of use instead of being kept live (as 64-bit register pairs)
+// across the whole kernel.
+__device__ __forceinline__ int fresh(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// slot of (row, direction) in the gradient exchange; 18 = not read (dummy)
+__device__ __forceinline__ int gslot(int row, int dir) {
+  if (row >= 6) return (row - 6) * 3 + dir;
+  if (row < 3) return row == dir ? 9 + row : 18;
+  if (row == 3) return dir == 0 ? 12 : (dir == 1 ? 13 : 18);
+  if (row == 4) return dir == 1 ? 14 : (dir == 2 ? 15 : 18);
+  return dir == 0 ? 16 : (dir == 2 ? 17 : 18);
+}
+
+template <class R, int O, int M>
+#ifndef EDG_LEVEL2_WAVES
+#define EDG_LEVEL2_WAVES 2
+#endif
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(EDG_LEVEL2_WAVES, 4)))
+void k_level2(KPtrs p, LevelArgs a) {
+  using RF = edg_gen::Ref<O>;
+  using L = Lds2<R, O, M>;
+  constexpr int B = RF::B, F = RF::F, FP = RF::FP;
+  constexpr int MM = M > 0 ? M : 1;
+  constexpr int NB0 = RF::MB1, NB1 = B - RF::MB1;
+  constexpr int NBX = NB0 > NB1 ? NB0 : NB1;
+  constexpr int JW = (NBX + LPE - 1) / LPE;      // owned memory modes per lane
+  constexpr int JB = (B + LPE - 1) / LPE;        // memory-variable layout
+  __shared__ R lds[L::TOTAL];
+
+  const int w = threadIdx.x >> 6;                 // wave (uniform)
+  const int lane = threadIdx.x & 63;
+  const int e = lane / LPE, r = lane % LPE;
+  const int ec = e < EPW ? e : EPW - 1;
+  const int q = e < EPW ? r : 0;
+  const int g = blockIdx.x;
+  const int elem = g * EPW + ec;
+  const bool valid = (e < EPW) && (elem < a.end);
+  const int slot = ec * LPE + q;
+  const int base = w ? RF::MB1 : 0;
+  const int nb = w ? NB1 : NB0;
+  constexpr int BS = L::BS, FS = L::FS;
+  R* const reg = lds + ec * L::REGION;
+  R* const fac = lds + ec * L::FACE;          // face area (surface phase only)
+  R* const grad = reg;
+  R* const coup = reg + L::GRAD;
+  R* const rx = reg + L::GRAD + L::COUP;
+
+  R* Qe = reinterpret_cast<R*>(p.Qe);
+  R* Qa = reinterpret_cast<R*>(p.Qa);
+  const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
+  const int* FI = p.FI + (size_t)elem * 8;
+  const size_t Kp = (size_t)p.Kp;
+  const size_t tstride = (size_t)4 * LPE * FP;
+
+  const int cl = cluster_of(a, elem);
+  const bool is_stress = q < 6;
+  int qi = 0, qj = 0;
+  if (q < 3) { qi = q; qj = q; }
+  else if (q == 3) { qi = 0; qj = 1; }
+  else if (q == 4) { qi = 1; qj = 2; }
+  else if (q == 5) { qi = 0; qj = 2; }
+  const R delta = q < 3 ? R(1) : R(0);
+
+  R G[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) G[c] = P[c];
+  const R rho_inv = P[9], lam = P[10], mu = P[11], zp = P[12], zs = P[13];
+  R al[MM], bl[MM], om[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    al[l] = M > 0 ? P[14 + 2 * l] : R(0);
+    bl[l] = M > 0 ? P[15 + 2 * l] : R(0);
+    om[l] = M > 0 ? R(a.omega[l]) : R(0);
+  }
+
+  // LDS offsets (elements of `grad`) this lane writes and reads
+  R* const gw0 = grad + gslot(q, 0) * BS;
+  R* const gw1 = grad + gslot(q, 1) * BS;
+  R* const gw2 = grad + gslot(q, 2) * BS;
+  int rA = 0, rB = 0, rC = 0;
+  if (!is_stress) {
+    const int i = q - 6;
+    rA = gslot(sym_index(i, 0), 0) * BS;
+    rB = gslot(sym_index(i, 1), 1) * BS;
+    rC = gslot(sym_index(i, 2), 2) * BS;
+  }
+  const int eA = gslot(6 + qi, qj) * BS, eB = gslot(6 + qj, qi) * BS;
+  const int d0 = gslot(6, 0) * BS, d1 = gslot(7, 1) * BS, d2 = gslot(8, 2) * BS;
+
+  R qe[NBX];
+  const size_t gbase = (size_t)g * B;
+#pragma unroll
+  for (int lb = 0; lb < NBX; ++lb)
+    qe[lb] = lb < nb ? Qe[(gbase + base + lb) * NSLOT + slot] : R(0);
+
+  // ------------------------------------------------ surface: finish step n
+  bool coup_pending = false;
+  if (a.kind != KIND_PREDICT) {
+    const int n = a.step_fin[cl];
+    const R* T1 = reinterpret_cast<const R*>(p.T1);
+    const R* T2 = reinterpret_cast<const R*>(p.T2);
+    const R* T3 = reinterpret_cast<const R*>(p.T3);
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+      const int i = 2 * w + ii;
+      const int nbr = FI[2 * i];
+      const int code = FI[2 * i + 1];
+      const int j = code & 15, rel = ((code >> 8) & 15) - 1;
+      const R* own = T1 + ((size_t)(n & 1) * Kp + elem) * tstride + (size_t)(i * LPE + q) * FP;
+      R* dmn = fac + ((i * 2 + 0) * LPE + q) * FS;
+      R* dpl = fac + ((i * 2 + 1) * LPE + q) * FS;
+#pragma unroll
+      for (int f = 0; f < FP; ++f) dmn[f] = own[f];
+      if (nbr >= 0) {
+        const size_t nbo = (size_t)nbr * tstride + (size_t)(j * LPE + q) * FP;
+        if (rel == 0) {
+          const R* s = T1 + (size_t)(n & 1) * Kp * tstride + nbo;
+#pragma unroll
+          for (int f = 0; f < FP; ++f) dpl[f] = s[f];
+        } else if (rel < 0) {
+          const R* s = T3 + (size_t)(n & 1) * Kp * tstride + nbo;
+#pragma unroll
+          for (int f = 0; f < FP; ++f) dpl[f] = s[f];
+        } else {
+          const int c = (n >> 1) & 1;
+          const R* s2 = T2 + (size_t)c * Kp * tstride + nbo;
+          if ((n & 1) == 0) {
+#pragma unroll
+            for (int f = 0; f < FP; ++f) dpl[f] = s2[f];
+          } else {
+            const R* s1 = T1 + (size_t)c * Kp * tstride + nbo;
+#pragma unroll
+            for (int f = 0; f < FP; ++f) dpl[f] = s1[f] - s2[f];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < FP; ++f) dpl[f] = R(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int rr = 0; rr < (4 * F + 2 * LPE - 1) / (2 * LPE); ++rr) {
+      const int t = q + LPE * (w + 2 * rr);
+      if (t < 4 * F) {
+        const int i = t / F, f = t % F;
+        const int code = FI[2 * i + 1];
+        const int bc = (code >> 4) & 15;
+        const R* fp = P + 20 + 6 * i;
+        R qm[9], qp[9], out[15];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          qm[k] = fac[((i * 2 + 0) * LPE + k) * FS + f];
+          qp[k] = fac[((i * 2 + 1) * LPE + k) * FS + f];
+        }
+        const R zpp = bc == 0 ? fp[4] : zp, zsp = bc == 0 ? fp[5] : zs;
+        godunov<R>(qm, qp, fp[0], fp[1], fp[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fp[3], bc, out);
+#pragma unroll
+        for (int k = 0; k < 15; ++k) fac[((i * 2 + k / 9) * LPE + k % 9) * FS + f] = out[k];
+      }
+    }
+    __syncthreads();
+    R da[NBX];
+    {
+      R pf[4 * FP];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) pf[i * FP + f] = fac[((i * 2 + 0) * LPE + q) * FS + f];
+      if (w == 0) RF::lift_p0(pf, qe); else RF::lift_p1(pf, qe);
+      if (M > 0) {
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) da[lb] = R(0);
+        if (is_stress) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int f = 0; f < FP; ++f) pf[i * FP + f] = fac[((i * 2 + 1) * LPE + q) * FS + f];
+          if (w == 0) RF::lift_p0(pf, da); else RF::lift_p1(pf, da);
+        }
+      }
+    }
+    if (M > 0) {
+      __syncthreads();
+      if (is_stress && e < EPW)
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb)
+          if (lb < nb) coup[q * BS + base + lb] = da[lb];
+      coup_pending = true;
+    }
+    __syncthreads();
+  }
+
+  R qa[JW][MM][6];
+  {
+  const int slotq = fresh(slot);
+#pragma unroll
+  for (int jw = 0; jw < JW; ++jw) {
+    const int lb = q + LPE * jw, b = base + lb;
+    const bool own = lb < nb;
+    const int jb = b / LPE;
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        R v = R(0);
+        if (M > 0 && own) {
+          v = Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slotq];
+          if (coup_pending) v += om[l] * coup[c * BS + b];
+        }
+        qa[jw][l][c] = v;
+      }
+  }
+  }
+  if (M > 0 && coup_pending) __syncthreads();
+
+  if (a.kind == KIND_NEIGHBOR) {
+    if (valid) {
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb)
+        if (lb < nb) Qe[(gbase + base + lb) * NSLOT + slot] = qe[lb];
+      if (M > 0)
+#pragma unroll
+        for (int jw = 0; jw < JW; ++jw) {
+          const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+          if (lb < nb)
+#pragma unroll
+            for (int l = 0; l < MM; ++l)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = qa[jw][l][c];
+        }
+    }
+    return;
+  }
+
+  // ------------------------------------------------ time kernel: predict step nn
+  const int nn = a.step_new[cl];
+  const int eflags = p.EF[elem];
+  const bool need_b2 = __syncthreads_or((eflags & EF_HAS_FINER) != 0);
+  const int rec_slot = p.rec_slot ? p.rec_slot[elem] : -1;
+  R de[NBX], te[NBX], t2[NBX];
+  R dm[JW][MM][6];
+#pragma unroll
+  for (int lb = 0; lb < NBX; ++lb) { de[lb] = qe[lb]; te[lb] = R(0); t2[lb] = R(0); }
+#pragma unroll
+  for (int jw = 0; jw < JW; ++jw)
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) dm[jw][l][c] = qa[jw][l][c];
+
+#pragma unroll 1
+  for (int d = 0; d < O; ++d) {
+    const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
+    const bool more = d + 1 < O;
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) te[lb] += c_d * de[lb];
+    if (need_b2)
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) t2[lb] += h_d * de[lb];
+    if (rec_slot >= 0 && valid) {
+      R* rd = reinterpret_cast<R*>(p.recD) + (((size_t)rec_slot * O + d) * LPE + q) * B + base;
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb)
+        if (lb < nb) rd[lb] = de[lb];
+    }
+    if (more) {
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb)
+        if (lb < nb) rx[q * BS + base + lb] = de[lb];
+    }
+    __syncthreads();
+    if (more) {
+      R full[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+      if (w == 0) RF::ck_grad_p0(full, G, gw0, gw1, gw2);
+      else RF::ck_grad_p1(full, G, gw0, gw1, gw2);
+    }
+    __syncthreads();
+    if (M > 0) {
+#pragma unroll
+      for (int jw = 0; jw < JW; ++jw) {
+        const int lb = q + LPE * jw, b = base + lb;
+        if (lb < nb) {
+          R eps[6];
+          if (more) {
+            eps[0] = grad[gslot(6, 0) * BS + b];
+            eps[1] = grad[gslot(7, 1) * BS + b];
+            eps[2] = grad[gslot(8, 2) * BS + b];
+            eps[3] = R(0.5) * (grad[gslot(6, 1) * BS + b] + grad[gslot(7, 0) * BS + b]);
+            eps[4] = R(0.5) * (grad[gslot(7, 2) * BS + b] + grad[gslot(8, 1) * BS + b]);
+            eps[5] = R(0.5) * (grad[gslot(6, 2) * BS + b] + grad[gslot(8, 0) * BS + b]);
+          }
+          R cp[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+          for (int l = 0; l < MM; ++l) {
+            const R tr = dm[jw][l][0] + dm[jw][l][1] + dm[jw][l][2];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) cp[c] -= bl[l] * dm[jw][l][c] + (c < 3 ? al[l] * tr : R(0));
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              qa[jw][l][c] -= om[l] * c_d * dm[jw][l][c];
+              if (more) dm[jw][l][c] = om[l] * (eps[c] - dm[jw][l][c]);
+            }
+          }
+          if (e < EPW)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) coup[c * BS + b] = cp[c];
+        }
+      }
+      __syncthreads();
+    }
+    if (is_stress) {
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) {
+        const int b = base + lb;
+        if (lb < nb) {
+          const R cq = M > 0 ? coup[q * BS + b] : R(0);
+          if (M > 0) qe[lb] += c_d * cq;
+          if (more) {
+            const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+            const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+            de[lb] = lam * delta * div + R(2) * mu * eps + cq;
+          }
+        }
+      }
+    } else if (more) {
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) {
+        const int b = base + lb;
+        if (lb < nb) de[lb] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+      }
+    }
+  }
+
+  // ------------------------------------------------ traces and volume
+#pragma unroll
+  for (int lb = 0; lb < NBX; ++lb)
+    if (lb < nb) rx[q * BS + base + lb] = te[lb];
+  __syncthreads();
+  {
+    R full[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+    R pt[2 * FP];
+    if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
+    const int el2 = fresh(elem);
+    const size_t own = ((size_t)(nn & 1) * Kp + el2) * tstride + (size_t)q * FP;
+    if (valid) {
+      R* T1 = reinterpret_cast<R*>(p.T1);
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) T1[own + (size_t)(2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+    }
+    if ((eflags & EF_HAS_COARSER) && valid) {
+      R* T3 = reinterpret_cast<R*>(p.T3);
+      const size_t o3 = ((size_t)((nn >> 1) & 1) * Kp + el2) * tstride + (size_t)q * FP;
+      if ((nn & 1) == 0) {
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int f = 0; f < FP; ++f) T3[o3 + (size_t)(2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+      } else {
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int f = 0; f < FP; ++f) T3[o3 + (size_t)(2 * w + ii) * LPE * FP + f] += pt[ii * FP + f];
+      }
+    }
+    if (w == 0) RF::vol_grad_p0(full, G, gw0, gw1, gw2);
+    else RF::vol_grad_p1(full, G, gw0, gw1, gw2);
+  }
+  __syncthreads();
+  if (M > 0) {
+#pragma unroll
+    for (int jw = 0; jw < JW; ++jw) {
+      const int lb = q + LPE * jw, b = base + lb;
+      if (lb < nb) {
+        R eps[6];
+        eps[0] = grad[gslot(6, 0) * BS + b];
+        eps[1] = grad[gslot(7, 1) * BS + b];
+        eps[2] = grad[gslot(8, 2) * BS + b];
+        eps[3] = R(0.5) * (grad[gslot(6, 1) * BS + b] + grad[gslot(7, 0) * BS + b]);
+        eps[4] = R(0.5) * (grad[gslot(7, 2) * BS + b] + grad[gslot(8, 1) * BS + b]);
+        eps[5] = R(0.5) * (grad[gslot(6, 2) * BS + b] + grad[gslot(8, 0) * BS + b]);
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) qa[jw][l][c] -= om[l] * eps[c];
+      }
+    }
+  }
+  if (is_stress) {
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) {
+      const int b = base + lb;
+      if (lb < nb) {
+        const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+        const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+        qe[lb] -= lam * delta * div + R(2) * mu * eps;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) {
+      const int b = base + lb;
+      if (lb < nb) qe[lb] -= rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+    }
+  }
+  if (need_b2) {   // B2 traces from the half-step integral (RX is free again)
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) rx[q * BS + base + lb] = t2[lb];
+    __syncthreads();
+    R full[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+    R pt[2 * FP];
+    if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
+    if (valid && (eflags & EF_HAS_FINER)) {
+      R* T2 = reinterpret_cast<R*>(p.T2);
+      const size_t own = ((size_t)(nn & 1) * Kp + fresh(elem)) * tstride + (size_t)q * FP;
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) T2[own + (size_t)(2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+    }
+  }
+
+  if (valid) {
+    const int sl = fresh(slot);
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) Qe[(gbase + base + lb) * NSLOT + sl] = qe[lb];
+    if (M > 0)
+#pragma unroll
+      for (int jw = 0; jw < JW; ++jw) {
+        const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+        if (lb < nb)
+#pragma unroll
+          for (int l = 0; l < MM; ++l)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + sl] = qa[jw][l][c];
+      }
+  }
+}
+
 // point sources: Q[stress] += -M phi(x_s) / |det J| * (S(t1) - S(t0)) for the
 // step of the source's element that ends at this level
 __device__ double stf_antiderivative(int kind, double p0, double p1, double t) {
@@ -594,7 +1077,10 @@ template <class R, int O, int M>
 int launch_level(const KPtrs& p, const LevelArgs& a, hipStream_t st) {
   const int grid = (a.end + EPW - 1) / EPW;
   if (grid <= 0) return 0;
-  hipLaunchKernelGGL((k_level<R, O, M>), dim3(grid), dim3(64), 0, st, p, a);
+  if constexpr (std::is_same<R, float>::value && O >= 4)
+    hipLaunchKernelGGL((k_level2<R, O, M>), dim3(grid), dim3(128), 0, st, p, a);
+  else
+    hipLaunchKernelGGL((k_level<R, O, M>), dim3(grid), dim3(64), 0, st, p, a);
   return (int)hipGetLastError();
 }
 

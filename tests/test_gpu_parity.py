@@ -75,7 +75,7 @@ def test_anelastic_lts_fp64(order):
     assert e <= TOL64 and es <= TOL64
 
 
-@pytest.mark.parametrize("order", [3, 5])
+@pytest.mark.parametrize("order", [3, 4, 5])
 def test_anelastic_lts_fp32(order):
     w = anelastic_setup("tiny", order, 3)
     orc = Oracle(w["mesh"], w["mat"], order, attn=w["attn"], n_clusters=3, lam=None, sources=w["src"],
@@ -95,15 +95,16 @@ def test_anelastic_lts_fp32(order):
     assert e <= TOL32 and es <= TOL32
 
 
-def test_elastic_lts_heterogeneous_fp64():
+@pytest.mark.parametrize("order,fp64", [(4, True), (5, False)])
+def test_elastic_lts_heterogeneous(order, fp64):
     """Elastic heterogeneous periodic mesh with 3 clusters (interior faces only,
     heterogeneous Godunov fluxes), several ragged groups."""
     mesh = synth.kuhn_cube_periodic(3, 1000.0, jitter=0.15, seed=3)
     K = mesh["tet_verts"].shape[0]
     mat = synth.random_materials(K, 7)
     w = dict(mesh=mesh, mat=mat)
-    orc = Oracle(mesh, mat, 4, n_clusters=3, lam=None)
-    ctx = gpu_context(w, 4, 3, True, mechanisms=0)
+    orc = Oracle(mesh, mat, order, n_clusters=3, lam=None)
+    ctx = gpu_context(w, order, 3, fp64, mechanisms=0)
     assert np.array_equal(ctx.get_clusters()["clusters"], orc.cl)
     q0 = synth.random_state(8, K, 9, orc.B)
     orc.set_initial(q0)
@@ -112,8 +113,8 @@ def test_elastic_lts_heterogeneous_fp64():
     orc.run(t)
     ctx.advance_to(t)
     e = parity(ctx.read_dofs(), orc.Q)
-    print(f"elastic heterogeneous LTS FP64: {e:.3e}")
-    assert e <= TOL64
+    print(f"elastic heterogeneous LTS O={order} {'FP64' if fp64 else 'FP32'}: {e:.3e}")
+    assert e <= (TOL64 if fp64 else TOL32)
 
 
 @pytest.mark.parametrize("ncube", [1, 2])
