@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # the paper's flop count per element update at O=5, m=3 when every zero of the
-# sparse matrices is skipped (Sec. VI-B, Table speedups_flops_loh3 discussion)
+# sparse matrices is skipped (Sec. VII-B (LOH.3, Performance), Table speedups_flops_loh3 discussion)
 PAPER_FLOPS_ALL_SPARSITY = 212688
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
 
@@ -186,7 +186,7 @@ def main():
         "unit": "GB/s" if frac_hbm >= frac_alu else "TFLOP/s",
         "frac": max(frac_hbm, frac_alu),
         "traffic": None,
-        "kernel": "k_level<float,5,3>",
+        "kernel": f"k_level2<float,{args.order},3>" if args.order >= 4 else f"k_level<float,{args.order},3>",
         "launches": ks["launches"],
         "avg_launch_ms": per_launch_ms,
         "element_updates_per_launch": upd_per_launch,

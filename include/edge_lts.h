@@ -5,13 +5,13 @@
  *
  * The operations follow Breuer & Heinecke, "Next-Generation Local Time
  * Stepping for the ADER-DG Finite Element Method" (arXiv 2202.10313):
- *   - the PDE and state vector: Sec. II, eq. hyp_sys (q = 6 stresses,
+ *   - the PDE and state vector: Sec. III (ADER-DG Finite Element Method), eq. hyp_sys (q = 6 stresses,
  *     3 velocities, 6m memory variables);
- *   - the element update: Sec. II-A (time kernel eq. ader_taylor with the
+ *   - the element update: Sec. III-A (Discrete Formulation) (time kernel eq. ader_taylor with the
  *     Cauchy-Kowalevski recursion, volume and surface kernels, eq. update);
- *   - clusters and lambda: Sec. IV-A (interval definition of C_1..C_Nc,
+ *   - clusters and lambda: Sec. V-A (Clustering) (interval definition of C_1..C_Nc,
  *     normalisation, lambda search in steps of 0.01);
- *   - buffers and schedule: Sec. IV-B (eq. lts_buffers and the walk-through
+ *   - buffers and schedule: Sec. V-B (Buffers and Algorithm; eq. lts_buffers and the walk-through
  *     of Fig. lts_scheme).
  * Point sources, receivers, boundary conditions and the Riemann solver are not
  * specified by the paper; the choices made are documented per function.
@@ -79,7 +79,7 @@ typedef struct {
  * failure; creation errors are returned only as codes). */
 int edg_create(const edg_config* cfg, edg_ctx** out);
 
-/* Mesh (Sec. II-A: conforming unstructured tetrahedra).  tet_verts [K][4]:
+/* Mesh (Sec. III-A (Discrete Formulation): conforming unstructured tetrahedra).  tet_verts [K][4]:
  * vertex ids, used only to match faces (three shared ids = a shared face;
  * periodic meshes reuse ids across the period); tet_xyz [K][4][3]: the tet's
  * vertex coordinates in the same local order; face_bc [K][4]: EDG_BC_* per
@@ -99,7 +99,7 @@ int edg_upload_mesh(edg_ctx* ctx, int64_t n_tets, const int64_t* tet_verts, cons
 int edg_upload_materials(edg_ctx* ctx, const double* rho, const double* vp, const double* vs,
                          const double* omega, const double* yp, const double* ys);
 
-/* Time clusters (Sec. IV-A).  cluster: [K] values 1..N_c in the caller's
+/* Time clusters (Sec. V-A (Clustering)).  cluster: [K] values 1..N_c in the caller's
  * element order (used as given; EDG_EINVAL if two face neighbours differ by
  * more than one), or NULL to derive them from the CFL steps, the interval
  * rule, normalisation and the lambda of the configuration.  Allocates the
@@ -164,13 +164,13 @@ void edg_destroy(edg_ctx* ctx);
 
 /* ---- host-only helpers (no device work; for tests and tools) ---------------- */
 
-/* Reference matrices of the library's basis (Sec. II-A): K [3][B][B] with
+/* Reference matrices of the library's basis (Sec. III-A (Discrete Formulation)): K [3][B][B] with
  * K[c][b][bb] = int phi_b d(phi_bb)/d xi_c and Ft [4][B][F] with
  * Ft[i][b][f] = int_{face i} phi_b psi_f over the unit triangle, face i
  * opposite local vertex i parameterised by its vertices in ascending order. */
 int edg_reference_matrices(int32_t order, double* K, double* Ft);
 
-/* Clustering of Sec. IV-A on host data: dt [K] CFL steps, nbr [K][4] face
+/* Clustering of Sec. V-A (Clustering) on host data: dt [K] CFL steps, nbr [K][4] face
  * neighbours (-1 = none); writes cluster [K] (1..N_c), lambda and speedup.
  * lambda_in <= 0 searches. */
 int edg_cluster_host(int64_t K, const double* dt, const int64_t* nbr, int32_t n_clusters,

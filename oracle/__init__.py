@@ -12,7 +12,7 @@ physical quadrature points and the neighbour's polynomial is evaluated at the
 same physical face points through its own reference map.  There are no
 precomputed flux matrices, no orientation bookkeeping and no factored
 relaxation frequencies; in exact arithmetic this equals the factored modal
-kernels of Sec. II (all integrands are polynomials and the rules are exact).
+kernels of Sec. III (ADER-DG Finite Element Method) (all integrands are polynomials and the rules are exact).
 
 Modules:
   poly     Dubiner orthonormal bases built as exact monomial polynomials

@@ -1,7 +1,7 @@
 """Clustered rate-2 local time stepping: CFL steps, clustering, normalisation,
 lambda search (test infrastructure: CPU oracle).
 
-Sec. IV-A (Clustering):
+Sec. V-A (Clustering):
   * dt_min = min_k dt_k^CFL;
   * N_c clusters C_l = [2^(l-1) lam dt_min, 2^l lam dt_min) for l < N_c and
     C_{N_c} = [2^(N_c-1) lam dt_min, inf), lam in (0.5, 1];
@@ -21,7 +21,7 @@ summed in cluster order; candidates lam = i/100 for i = 51..100; ties go to the
 larger lam.  Interval membership uses the products (lam*dt_min)*2^(l-1)
 compared with dt_k in FP64 (the lower bound belongs to the interval).
 
-Pins (tests/test_oracle_lts.py): the worked examples of Sec. IV-A
+Pins (tests/test_oracle_lts.py): the worked examples of Sec. V-A (Clustering)
 (3 lam dt_min -> C_2; a C_3 element next to a C_1 element moves to C_2;
 lam = 0.75 intervals); the normalisation fixpoint against brute-force graph
 distances; the lambda search against exhaustive evaluation.

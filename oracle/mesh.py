@@ -1,7 +1,7 @@
 """Face adjacency and affine tetrahedron geometry (test infrastructure: CPU
 oracle).
 
-Sec. II-A: conforming tetrahedral meshes; element k has four face neighbours
+Sec. III-A (Discrete Formulation): conforming tetrahedral meshes; element k has four face neighbours
 k_1..k_4 (the surface kernel needs them).  Face i of a tet is the face opposite
 its local vertex i.  Two faces match when they carry the same three vertex ids
 (periodic meshes reuse ids across the period while the coordinates stay

@@ -1,7 +1,7 @@
 """Anelastic wave equations: Jacobians, coupling and the Riemann solver (test
 infrastructure: CPU oracle).
 
-Sec. II (eq. hyp_sys): q_t + A q_x + B q_y + C q_z = E q with
+Sec. III (ADER-DG Finite Element Method, eq. hyp_sys): q_t + A q_x + B q_y + C q_z = E q with
 q = (sigma_xx, sigma_yy, sigma_zz, sigma_xy, sigma_yz, sigma_xz, u, v, w,
      theta^1_xx .. theta^1_xz, ..., theta^m_xx .. theta^m_xz).
 The paper names u, v and "v" for the velocities; the third is read as w.
@@ -18,7 +18,7 @@ references; this oracle writes out the standard velocity-stress system:
 with a_l = (lambda + 2 mu) Y^P_l - 2 mu Y^S_l (= lambda Y^lambda_l) and
 b_l = 2 mu Y^S_l.  lambda, mu are the unrelaxed moduli from (rho, vp, vs).
 The relaxation sign is the decaying one (-omega_l); the time-kernel equation of
-Sec. II-A prints +omega_l, the volume kernel -omega_l, and only the latter is
+Sec. III-A (Discrete Formulation) prints +omega_l, the volume kernel -omega_l, and only the latter is
 stable.
 
 Riemann solver (the paper gives none): Godunov.  For a face with unit normal n

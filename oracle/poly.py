@@ -1,7 +1,7 @@
 """Orthonormal modal bases on the unit tetrahedron and unit triangle (test
 infrastructure: CPU oracle).
 
-Sec. II-A (Discrete Formulation) takes the element basis from the tetrahedral
+Sec. III-A (Discrete Formulation) takes the element basis from the tetrahedral
 expansion of Karniadakis & Sherwin, with B(O) = O(O+1)(O+2)/6 functions
 (B(4)=20, B(5)=35) and a diagonal mass matrix; faces use F(O) = O(O+1)/2
 triangular functions (F(5)=15).  Here each basis function is built *exactly*

@@ -1,7 +1,7 @@
 """ADER-DG element update with clustered rate-2 LTS (test infrastructure: CPU
 oracle, FP64, quadrature form).
 
-What is computed, in the paper's order and notation (Sec. II-A, IV-B):
+What is computed, in the paper's order and notation (Sec. III-A Discrete Formulation, Sec. V-B Buffers and Algorithm):
 
   time kernel      d^{d+1}Q = L(d^dQ): the Cauchy-Kowalevski step, written
                    here as the L2 projection of -sum_d A_d dq/dx_d + E q onto
@@ -18,7 +18,7 @@ What is computed, in the paper's order and notation (Sec. II-A, IV-B):
                    B3 = B1 if n even, B3 + B1 if n odd (eq. lts_buffers);
   neighbour data   same cluster: B1 of the neighbour; finer neighbour: its B3;
                    coarser neighbour: its B2 in the first half of its step,
-                   B1 - B2 in the second (Sec. IV-B walk-through);
+                   B1 - B2 in the second (Sec. V-B (Buffers and Algorithm) walk-through);
   schedule         per finest level: first all updates of the clusters whose
                    step ends there, then all predictions of the clusters whose
                    step starts there.
@@ -32,7 +32,7 @@ element's step, during its prediction (the 9 elastic quantities).
 Pins: tests/test_oracle_solver.py (plane waves, convergence order, ODE case
 against expm, energy decay, momentum conservation, polynomial exactness,
 GTS == single-cluster LTS) and tests/test_oracle_lts.py (the buffer walk-
-through of Sec. IV-B traced element by element).
+through of Sec. V-B (Buffers and Algorithm) traced element by element).
 """
 from __future__ import annotations
 
@@ -353,7 +353,7 @@ class Oracle:
     def run(self, t_end):
         """Advance every element from the current sync point to t_end (a
         multiple of the coarsest cluster step), clusters interleaved per finest
-        level as in Sec. IV-B."""
+        level as in Sec. V-B (Buffers and Algorithm)."""
         levels_per_cycle = 2 ** (self.n_clusters - 1)
         t_now = self.level * self.dt_cluster[0]
         cycles = (t_end - t_now) / self.sync_dt

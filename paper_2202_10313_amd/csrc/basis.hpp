@@ -2,7 +2,7 @@
 // update (host side, double precision).
 //
 // Element basis: the Karniadakis-Sherwin (Dubiner) tetrahedral expansion named
-// in Sec. II-A, orthonormal on the unit tetrahedron (0,0,0),(1,0,0),(0,1,0),
+// in Sec. III-A (Discrete Formulation), orthonormal on the unit tetrahedron (0,0,0),(1,0,0),(0,1,0),
 // (0,0,1) so that the mass matrix is the identity (the paper's "inverse,
 // diagonal mass matrix" is then a scalar 1/|det J|).  B(O) = O(O+1)(O+2)/6
 // functions ordered by total degree, then i descending, then j descending.

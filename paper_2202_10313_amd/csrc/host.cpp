@@ -154,7 +154,7 @@ void inverse3(const double J[9], double G[9], double& det) {
   G[8] = (J[0] * J[4] - J[1] * J[3]) * id;
 }
 
-// Sec. IV-A clustering: assign by interval, normalise to the neighbour rule,
+// Sec. V-A (Clustering): assign by interval, normalise to the neighbour rule,
 // optional lambda search maximising K / sum_l n_l / (2^(l-1) lambda).
 void cluster_assign(int64_t K, const double* dt, double dt_min, double lam, int Nc, std::vector<int>& cl) {
   cl.assign(K, 0);

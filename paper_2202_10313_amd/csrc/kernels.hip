@@ -1,9 +1,9 @@
 // HIP kernels (gfx950) of the ADER-DG element update with clustered rate-2
 // LTS: time kernel (Cauchy-Kowalevski), volume kernel, surface kernel with the
 // Godunov flux, anelastic relaxation, B1/B2/B3 buffer output, point sources,
-// receivers.  Sec. II-A (eqs. ader_taylor, ader_derivative_elastic,
+// receivers.  Sec. III-A (Discrete Formulation; eqs. ader_taylor, ader_derivative_elastic,
 // ader_derivative_anelastic, volume, local/neigh surface kernels, update) and
-// Sec. IV-B (eq. lts_buffers and the buffer consumption rules).
+// Sec. V-B (Buffers and Algorithm; eq. lts_buffers and the buffer consumption rules).
 //
 // Work mapping.  One wave (64 lanes) owns 7 elements; lane = 9*e + q holds the
 // modal row q (0..5 stresses xx,yy,zz,xy,yz,xz; 6..8 velocities u,v,w) of
