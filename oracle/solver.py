@@ -69,7 +69,7 @@ def stf_integral(kind, params, t):
 
 class Oracle:
     def __init__(self, mesh, mat, order, attn=None, n_clusters=1, cfl=0.5, lam=1.0,
-                 clusters=None, sources=None, receivers=None, ghost=None):
+                 clusters=None, sources=None, receivers=None, ghost=None, dt_min=None):
         self.O = order
         self.B = n_basis(order)
         self.F = n_face_basis(order)
@@ -144,7 +144,8 @@ class Oracle:
             self.speedup = _lts.speedup(self.cl, self.lam_lts, n_clusters)
         else:
             self.cl, self.lam_lts, self.speedup = _lts.cluster(self.dt_cfl, self.nbr, n_clusters, lam)
-        self.dt_min = float(self.dt_cfl.min())
+        # dt_min may be imposed (a sub-mesh advanced with the steps of a larger mesh)
+        self.dt_min = float(self.dt_cfl.min()) if dt_min is None else float(dt_min)
         self.dt_cluster = _lts.cluster_dt(self.dt_min, self.lam_lts, n_clusters)
         self.dt_elem = self.dt_cluster[self.cl - 1]
         self.sync_dt = self.dt_cluster[-1]

@@ -299,6 +299,9 @@ int set_dofs_t(edg_ctx* c, const double* dofs) {
     const auto& C = perm_matrix(c, c->perm[k]);
     for (int q = 0; q < NQ; ++q) {
       const double* src = dofs + ((size_t)k * NQ + q) * B;
+      bool zero = true;
+      for (int bb = 0; bb < B && zero; ++bb) zero = src[bb] == 0.0;
+      if (zero) continue;   // the staging buffer is already zero
       for (int b = 0; b < B; ++b) {
         double s = 0.0;
         for (int bb = 0; bb < B; ++bb) s += C[b * B + bb] * src[bb];
@@ -327,9 +330,16 @@ int get_dofs_t(edg_ctx* c, double* out) {
     const int64_t ki = c->user_to_internal[k];
     const auto& C = perm_matrix(c, c->perm[k]);
     for (int q = 0; q < NQ; ++q) {
-      for (int b = 0; b < B; ++b)
+      bool zero = true;
+      for (int b = 0; b < B; ++b) {
         row[b] = q < 9 ? (double)he[qe_index(c, ki, q, b)] : (double)ha[qa_index(c, ki, (q - 9) / 6, (q - 9) % 6, b)];
+        zero = zero && row[b] == 0.0;
+      }
       double* dst = out + ((size_t)k * NQ + q) * B;
+      if (zero) {
+        for (int bb = 0; bb < B; ++bb) dst[bb] = 0.0;
+        continue;
+      }
       for (int bb = 0; bb < B; ++bb) {
         double s = 0.0;
         for (int b = 0; b < B; ++b) s += C[b * B + bb] * row[b];

@@ -81,3 +81,47 @@ def random_direction_wavevector(seed, L=1000.0):
     if not np.any(m):
         m[np.argmax(np.abs(n))] = 1.0
     return m / np.linalg.norm(m), 2 * math.pi * np.linalg.norm(m) / L
+
+
+def face_adjacency(tet_verts):
+    """[K,4] face neighbours (-1 = none) by sorting face vertex triples
+    (vectorised, for million-element meshes)."""
+    K = tet_verts.shape[0]
+    rows = []
+    for i in range(4):
+        f = np.sort(tet_verts[:, [m for m in range(4) if m != i]], axis=1)
+        rows.append(np.concatenate([f, np.arange(K)[:, None], np.full((K, 1), i)], axis=1))
+    F = np.concatenate(rows)
+    F = F[np.lexsort((F[:, 2], F[:, 1], F[:, 0]))]
+    same = np.nonzero(np.all(F[1:, :3] == F[:-1, :3], axis=1))[0]
+    nbr = -np.ones((K, 4), dtype=np.int64)
+    a, b = F[same], F[same + 1]
+    nbr[a[:, 3], a[:, 4]] = b[:, 3]
+    nbr[b[:, 3], b[:, 4]] = a[:, 3]
+    return nbr
+
+
+def graph_ball(nbr, seeds, radius):
+    """Element ids within `radius` face hops of the seeds."""
+    seen = np.zeros(nbr.shape[0], dtype=bool)
+    seen[seeds] = True
+    front = np.asarray(seeds)
+    for _ in range(radius):
+        cand = nbr[front].ravel()
+        cand = np.unique(cand[cand >= 0])
+        cand = cand[~seen[cand]]
+        seen[cand] = True
+        front = cand
+    return np.nonzero(seen)[0]
+
+
+def submesh(mesh, ids, nbr):
+    """Sub-mesh of the elements `ids`: faces whose neighbour is outside become
+    absorbing."""
+    idx = np.asarray(ids)
+    inside = np.zeros(mesh["tet_verts"].shape[0], dtype=bool)
+    inside[idx] = True
+    bc = mesh["face_bc"][idx].copy()
+    cut = (nbr[idx] >= 0) & ~inside[np.maximum(nbr[idx], 0)]
+    bc[cut] = 2
+    return dict(tet_verts=mesh["tet_verts"][idx], tet_xyz=mesh["tet_xyz"][idx], face_bc=bc)
