@@ -15,7 +15,7 @@ advances by its own steps).  The timed region is one edg_advance_to call over
 second is the value.  The roofline entry uses the per-launch durations of
 the element-update kernel from HIP events recorded on the library's stream
 during the same timed region.  The CPU baseline times the FP64 oracle on a
-bounded sample (a 6 x 6-column box of the same construction, one cycle).
+bounded sample (a 6 x 6-column box of the same construction, three cycles).
 """
 from __future__ import annotations
 
@@ -40,7 +40,24 @@ VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # the paper's flop count per element update at O=5, m=3 when every zero of the
 # sparse matrices is skipped (Sec. VII-B (LOH.3, Performance), Table speedups_flops_loh3 discussion)
 PAPER_FLOPS_ALL_SPARSITY = 212688
+# HBM traffic of the element-update kernel: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by what the counter reads for a device copy of known
+# size, summed over the four launches of a steady-state LTS cycle and divided by
+# the cycle's element updates.  Valid only for the kernel sources it was taken
+# on (their SHA-256 below); after any change the roofline reports null.
+TRAFFIC_BYTES_PER_UPDATE = 29238.0
+TRAFFIC_SOURCES_SHA256 = "2cb449ed35c015651d5d8b07d6d85f75099c8213796efb540c883639446fcfd9"
+KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2202_10313_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def face_neighbours(tet_verts):
@@ -80,9 +97,10 @@ def algorithmic_bytes_per_update(cl, nbr, order, m, n_clusters, word=4):
     return float(np.sum(per * weight) / np.sum(weight))
 
 
-def cpu_baseline(budget_s=30.0):
+def cpu_baseline(cycles=3):
     """Oracle (FP64 NumPy) on a 6 x 6-column box of the workload's
-    construction (same spacing, layering and material recipe), one LTS cycle."""
+    construction (same spacing, layering and material recipe), `cycles` LTS
+    cycles (about 15 s of CPU time)."""
     from oracle.solver import Oracle
     dz = [100.0] * 4 + [200.0] * 3 + [300.0] * 30
     h = 20000.0 / 67
@@ -93,12 +111,12 @@ def cpu_baseline(budget_s=30.0):
     orc = Oracle(mesh, mat, 5, attn=attn, n_clusters=3, lam=None)
     orc.set_initial(synth.random_state(1, orc.K, 27, orc.B))
     c0, t0 = time.process_time(), time.perf_counter()
-    orc.run(orc.sync_dt)
+    orc.run(cycles * orc.sync_dt)
     t1, c1 = time.perf_counter(), time.process_time()
     return {"value": orc.updates / (t1 - t0), "unit": "elem-updates/s", "cores": max(1, round((c1 - c0) / (t1 - t0))),
             "kind": "oracle",
             "sample": f"FP64 oracle, {orc.K}-tet 6x6-column box of the same construction, O=5, m=3, N_c=3, "
-                      f"one LTS cycle ({orc.updates} element updates in {t1 - t0:.1f} s)"}
+                      f"{cycles} LTS cycles ({orc.updates} element updates in {t1 - t0:.1f} s)"}
 
 
 def main():
@@ -179,13 +197,17 @@ def main():
     frac_hbm = achieved_gbs / HBM_PEAK_GBS
     frac_alu = achieved_tf / VALU_FP32_PEAK_TFLOPS
     counts = np.bincount(cl, minlength=4)[1:]
+    traffic = None
+    if args.order == 5 and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256:
+        traffic = TRAFFIC_BYTES_PER_UPDATE * upd_per_launch
     roofline = {
         "bound": "hbm" if frac_hbm >= frac_alu else "alu",
         "achieved": achieved_gbs if frac_hbm >= frac_alu else achieved_tf,
         "peak": HBM_PEAK_GBS if frac_hbm >= frac_alu else VALU_FP32_PEAK_TFLOPS,
         "unit": "GB/s" if frac_hbm >= frac_alu else "TFLOP/s",
         "frac": max(frac_hbm, frac_alu),
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "bytes/launch",
         "kernel": f"k_level2<float,{args.order},3>" if args.order >= 4 else f"k_level<float,{args.order},3>",
         "launches": ks["launches"],
         "avg_launch_ms": per_launch_ms,

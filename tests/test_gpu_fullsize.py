@@ -1,0 +1,172 @@
+"""Parity at the benchmark's full size and launch configuration: the 996,558-tet
+layered box, order 5, 3 mechanisms, N_c = 3 with the searched lambda, FP32,
+launched on torch's current stream.
+
+The oracle cannot advance a million elements, so the check is local.  After
+one LTS cycle (4 steps of the finest cluster) the state of an element depends
+only on initial data within 4 face hops: every update ending at time t reads
+neighbour predictions that start at an earlier multiple of the finest step
+(Sec. V-B (Buffers and Algorithm): B1/B2/B3 hold predictions from the start of
+the neighbour's step), so each hop costs one of the cycle's four finest steps.
+The test therefore
+
+  * compares the clustering of the whole mesh (ids, lambda, dt_min, speedup)
+    with the oracle's, bit for bit;
+  * fills random initial data into the union U of 4-hop balls around sampled
+    elements (each cluster's interior, cluster interfaces in both directions,
+    free-surface and absorbing boundaries, the first and last element of each
+    cluster -- the ragged tails of the cluster ranges -- and the elements
+    holding the source and a receiver), zero elsewhere;
+  * advances the whole mesh one cycle on the GPU and the oracle on U alone
+    (faces leaving U absorbing, the full mesh's clusters, lambda and dt_min);
+  * compares every sampled element's DOFs and the receiver's seismogram, and
+    checks the properties that hold at any size: the element-update count of
+    the cycle and that every element more than 4 hops from U stays exactly
+    zero.
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import face_adjacency, graph_ball, groups, seis_parity, submesh
+
+pytestmark = pytest.mark.gpu
+
+ORDER, MECH, NC = 5, 3, 3
+TOL_FP32 = 2e-5
+HOPS = 4          # finest steps per cycle with N_c = 3
+
+
+def element_parity(a, b):
+    """Per element: max over quantity groups of ||a - b|| / ||b|| (group norms)."""
+    worst = 0.0
+    for (g0, g1) in groups(a.shape[0]):
+        den = np.linalg.norm(b[g0:g1]) or 1.0
+        worst = max(worst, np.linalg.norm(a[g0:g1] - b[g0:g1]) / den)
+    return worst
+
+
+def pick_samples(rng, cl, nbr, bc, src_elem, rec_elem):
+    ncl = np.where(nbr >= 0, cl[np.maximum(nbr, 0)], cl[:, None])
+    finer = np.any(ncl < cl[:, None], axis=1)
+    coarser = np.any(ncl > cl[:, None], axis=1)
+    free = np.any(bc == synth.BC_FREE, axis=1)
+    absorb = np.any(bc == synth.BC_ABSORB, axis=1)
+    picks = {}
+
+    def take(name, mask, n=2):
+        ids = np.nonzero(mask)[0]
+        assert len(ids) > 0, name
+        picks[name] = rng.choice(ids, size=min(n, len(ids)), replace=False)
+
+    for l in range(1, NC + 1):
+        take(f"C{l} interior", (cl == l) & ~finer & ~coarser)
+        ids = np.nonzero(cl == l)[0]
+        picks[f"C{l} first/last"] = np.array([ids[0], ids[-1]])
+    take("finer neighbour (C2)", (cl == 2) & finer)
+    take("finer neighbour (C3)", (cl == 3) & finer)
+    take("coarser neighbour (C1)", (cl == 1) & coarser)
+    take("coarser neighbour (C2)", (cl == 2) & coarser)
+    take("free surface", free & ~absorb)
+    take("absorbing side/bottom", absorb & ~free)
+    take("free + absorbing edge", free & absorb, 1)
+    picks["source"] = np.array([src_elem])
+    picks["receiver"] = np.array([rec_elem])
+    return picks
+
+
+def test_full_size_sampled_parity():
+    import torch
+    from oracle import lts as olts
+    from oracle import mesh as omesh
+    from oracle.solver import Oracle
+    from paper_2202_10313_amd import STF_RICKER, Context
+
+    # the benchmark's workload (same generators and seeds)
+    mesh = synth.loh_like_box("full", seed=20)
+    K = mesh["tet_verts"].shape[0]
+    assert K == 996558
+    mat = synth.layered_materials(mesh, 21)
+    attn = synth.attenuation_inputs(mat, MECH, 0.1, 10.0)
+    src = synth.ricker_sources(22, 1, ((5000.0, 15000.0), (5000.0, 15000.0)), (1000.0, 5000.0),
+                               fc_range=(2.0, 2.0))
+    # t0 = 0 so that the moment rate is ~1 during the cycle (the benchmark's
+    # t0 = 1.5/fc would inject ~1e-10 of the state)
+    src_params = np.array([[2.0, 0.0]])
+
+    # clustering of the whole mesh by the oracle
+    nbr = face_adjacency(mesh["tet_verts"])
+    geo = omesh.geometry(mesh["tet_xyz"])
+    dt_cfl = olts.cfl_steps(geo["inradius"], mat["vp"], ORDER, 0.5)
+    cl, lam, speedup = olts.cluster(dt_cfl, nbr, NC, None)
+    dt_min = float(dt_cfl.min())
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = Context(ORDER, mechanisms=MECH, n_clusters=NC, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream)
+    ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+    ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+    ctx.upload_clusters(None)
+    info = ctx.get_clusters()
+    assert np.array_equal(info["clusters"], cl)
+    assert info["lam"] == lam
+    assert abs(info["dt_min"] - dt_min) <= 1e-14 * dt_min
+    assert abs(info["speedup"] - speedup) <= 1e-12 * speedup
+    sync = info["sync_dt"]
+    assert abs(sync - 4 * lam * dt_min) <= 1e-14 * sync
+
+    # samples and the patch union
+    src_elem = int(omesh.locate_points(mesh["tet_xyz"], src["xyz"])[0][0])
+    rng = np.random.default_rng(5)
+    free_ids = np.nonzero(np.any(mesh["face_bc"] == synth.BC_FREE, axis=1))[0]
+    rec_elem = int(rng.choice(free_ids))
+    rec_xyz = mesh["tet_xyz"][rec_elem].mean(axis=0)[None]
+    picks = pick_samples(rng, cl, nbr, mesh["face_bc"], src_elem, rec_elem)
+    samples = np.unique(np.concatenate(list(picks.values())))
+    U = graph_ball(nbr, samples, HOPS)
+    print(f"[fullsize] {len(samples)} samples, patch union {len(U)} elements", flush=True)
+
+    q0 = np.zeros((K, 9 + 6 * MECH, ctx.B))
+    q0[U] = synth.random_state(7, len(U), 9 + 6 * MECH, ctx.B)
+    ctx.set_initial(q0)
+    ctx.set_sources(src["xyz"], src["moment"], STF_RICKER, src_params)
+    n_samp = 5
+    ctx.set_receivers(rec_xyz, sync / n_samp, n_samp)
+    u0 = ctx.element_updates()
+    ctx.advance_to(sync)
+    torch.cuda.synchronize()
+    counts = np.bincount(cl, minlength=NC + 1)[1:]
+    assert ctx.element_updates() - u0 == sum(int(counts[l]) << (NC - 1 - l) for l in range(NC))
+    q1 = ctx.read_dofs()
+    seis = ctx.read_receivers()
+    ctx.close()
+    del q0
+
+    # nothing outside the dependency cone of U (or of the source) changed
+    reach = np.zeros(K, dtype=bool)
+    reach[graph_ball(nbr, np.concatenate([U, [src_elem]]), HOPS)] = True
+    assert not np.any(q1[~reach]), "non-zero DOFs outside the 4-hop cone of the initial data"
+    assert np.all(np.isfinite(q1[reach]))
+
+    # the oracle on the patch union
+    sub = submesh(mesh, U, nbr)
+    sub_mat = {k: mat[k][U] for k in ("rho", "vp", "vs")}
+    sub_attn = dict(omega=attn["omega"], yp=attn["yp"][U], ys=attn["ys"][U])
+    orc = Oracle(sub, sub_mat, ORDER, attn=sub_attn, n_clusters=NC, cfl=0.5, lam=lam, clusters=cl[U],
+                 dt_min=dt_min,
+                 sources=dict(xyz=src["xyz"], moment=src["moment"], stf_kind=STF_RICKER, stf_params=src_params),
+                 receivers=dict(xyz=rec_xyz, dt_sample=sync / n_samp, n_samples=n_samp))
+    assert abs(orc.sync_dt - sync) <= 1e-14 * sync
+    orc.set_initial(synth.random_state(7, len(U), 9 + 6 * MECH, ctx.B))
+    orc.run(sync)
+
+    errs = {}
+    for name, ids in picks.items():
+        for k in ids:
+            errs[(name, int(k))] = element_parity(q1[k], orc.Q[np.searchsorted(U, k)])
+    worst = max(errs, key=errs.get)
+    print(f"[fullsize] worst element {worst}: {errs[worst]:.2e}", flush=True)
+    assert errs[worst] <= TOL_FP32, errs
+    e_rec = seis_parity(seis, orc.seis)
+    print(f"[fullsize] receiver parity {e_rec:.2e}", flush=True)
+    assert e_rec <= TOL_FP32
