@@ -157,6 +157,70 @@ RefMats reference_matrices(int O) {
   return R;
 }
 
+std::vector<double> direction_matrices(const RefMats& M, const Directions& D) {
+  const int B = M.B;
+  std::vector<double> Kd(3 * B * B, 0.0);
+  for (int k = 0; k < 3; ++k)
+    for (int c = 0; c < 3; ++c)
+      if (D.V[3 * k + c] != 0.0)
+        for (int i = 0; i < B * B; ++i) Kd[k * B * B + i] += D.V[3 * k + c] * M.K[c * B * B + i];
+  return Kd;
+}
+
+Directions sparse_directions(int O) {
+  const RefMats M = reference_matrices(O);
+  const int B = M.B;
+  const double vals[5] = {-1.0, -0.5, 0.0, 0.5, 1.0};
+  std::vector<std::array<double, 3>> cand;
+  std::vector<int> nnz;
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b)
+      for (int c = 0; c < 5; ++c) {
+        const std::array<double, 3> v = {vals[a], vals[b], vals[c]};
+        const double mx = std::max(std::fabs(v[0]), std::max(std::fabs(v[1]), std::fabs(v[2])));
+        const double first = v[0] != 0.0 ? v[0] : (v[1] != 0.0 ? v[1] : v[2]);
+        if (mx != 1.0 || first <= 0.0) continue;
+        int n = 0;
+        for (int i = 0; i < B * B; ++i)
+          n += std::fabs(v[0] * M.K[i] + v[1] * M.K[B * B + i] + v[2] * M.K[2 * B * B + i]) > 1e-12;
+        cand.push_back(v);
+        nnz.push_back(n);
+      }
+  const int n = (int)cand.size();
+  int best[3] = {-1, -1, -1}, best_cost = 1 << 30;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      for (int k = j + 1; k < n; ++k) {
+        const int cost = nnz[i] + nnz[j] + nnz[k];
+        if (cost >= best_cost) continue;
+        const auto &x = cand[i], &y = cand[j], &z = cand[k];
+        const double det = x[0] * (y[1] * z[2] - y[2] * z[1]) - x[1] * (y[0] * z[2] - y[2] * z[0]) +
+                           x[2] * (y[0] * z[1] - y[1] * z[0]);
+        if (std::fabs(det) < 1e-9) continue;
+        best_cost = cost;
+        best[0] = i; best[1] = j; best[2] = k;
+      }
+  Directions D;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) D.V[3 * r + c] = cand[best[r]][c];
+    D.nnz[r] = nnz[best[r]];
+  }
+  const double* V = D.V;
+  const double det = V[0] * (V[4] * V[8] - V[5] * V[7]) - V[1] * (V[3] * V[8] - V[5] * V[6]) +
+                     V[2] * (V[3] * V[7] - V[4] * V[6]);
+  const double id = 1.0 / det;
+  D.Vinv[0] = (V[4] * V[8] - V[5] * V[7]) * id;
+  D.Vinv[1] = (V[2] * V[7] - V[1] * V[8]) * id;
+  D.Vinv[2] = (V[1] * V[5] - V[2] * V[4]) * id;
+  D.Vinv[3] = (V[5] * V[6] - V[3] * V[8]) * id;
+  D.Vinv[4] = (V[0] * V[8] - V[2] * V[6]) * id;
+  D.Vinv[5] = (V[2] * V[3] - V[0] * V[5]) * id;
+  D.Vinv[6] = (V[3] * V[7] - V[4] * V[6]) * id;
+  D.Vinv[7] = (V[1] * V[6] - V[0] * V[7]) * id;
+  D.Vinv[8] = (V[0] * V[4] - V[1] * V[3]) * id;
+  return D;
+}
+
 std::vector<double> vertex_permutation_matrix(int O, const int perm[4]) {
   // q_new(xi_new) is the same polynomial as q_old(xi_old): project
   // phi_bb(xi_old(xi_new)) onto phi_b(xi_new).  Barycentrics: lambda_new[m] =

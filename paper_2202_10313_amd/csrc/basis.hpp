@@ -145,6 +145,22 @@ struct RefMats {
 };
 RefMats reference_matrices(int O);
 
+// Three independent reference directions w_k = sum_c V[k][c] d/dxi_c along
+// which this basis's derivative matrices have the fewest non-zeros (entries of
+// V in {0, +-1/2, +-1}, largest entry 1, first non-zero positive; ties go to
+// the earliest triple in enumeration order).  A gradient taken along them is
+// mapped to physical coordinates by G' = V^-T G (G[c][d] = d xi_c / d x_d):
+// sum_k G'[k][d] w_k = sum_c G[c][d] d/dxi_c.  The stiffness products then
+// cost sum_k nnz(sum_c V[k][c] K_c) FMAs per row instead of sum_c nnz(K_c)
+// (O=5: 364 instead of 647).
+struct Directions {
+  double V[9], Vinv[9];
+  int nnz[3];
+};
+Directions sparse_directions(int O);
+// K' [3][B][B] with K'[k] = sum_c V[k][c] K[c] (same layout as RefMats::K)
+std::vector<double> direction_matrices(const RefMats& M, const Directions& D);
+
 // Coefficients of the same polynomial after a permutation of the tet's local
 // vertices: if new local vertex m is old local vertex perm[m], then
 // q_new[b] = sum_bb C[b][bb] q_old[bb].  C is orthogonal (B x B).

@@ -34,6 +34,7 @@ struct DevBuf {
 struct edg_ctx {
   edg_config cfg{};
   int O = 0, B = 0, F = 0, FP = 0, M = 0, NQ = 0;
+  edg::Directions dirs{};   // stiffness directions of the generated kernels
   std::string err;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -230,7 +231,14 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
     R* p = &P[(size_t)ki * NPARAM];
     const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
     const double mu = rho * vs * vs, lam = rho * vp * vp - 2.0 * mu;
-    for (int j = 0; j < 9; ++j) p[j] = R(c->Gm[k * 9 + j]);
+    // G' = V^-T G for the library's stiffness directions
+    const double* G = &c->Gm[(size_t)k * 9];
+    for (int kk = 0; kk < 3; ++kk)
+      for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        for (int cc = 0; cc < 3; ++cc) s += c->dirs.Vinv[cc * 3 + kk] * G[cc * 3 + d];
+        p[kk * 3 + d] = R(s);
+      }
     p[9] = R(1.0 / rho);
     p[10] = R(lam);
     p[11] = R(mu);
@@ -502,6 +510,7 @@ int edg_create(const edg_config* cfg, edg_ctx** out) {
   c->FP = (c->F + 3) / 4 * 4;
   c->M = cfg->mechanisms;
   c->NQ = 9 + 6 * c->M;
+  c->dirs = edg::sparse_directions(c->O);
   if (cfg->hip_stream) {
     c->stream = (hipStream_t)cfg->hip_stream;
   } else {

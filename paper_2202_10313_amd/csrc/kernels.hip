@@ -576,7 +576,7 @@ void k_level2(KPtrs p, LevelArgs a) {
   constexpr int JB = (B + LPE - 1) / LPE;        // memory-variable layout
   __shared__ R lds[L::TOTAL];
 
-  const int w = threadIdx.x >> 6;                 // wave (uniform)
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave (uniform)
   const int lane = threadIdx.x & 63;
   const int e = lane / LPE, r = lane % LPE;
   const int ec = e < EPW ? e : EPW - 1;
@@ -783,14 +783,21 @@ void k_level2(KPtrs p, LevelArgs a) {
   }
 
   // ------------------------------------------------ time kernel: predict step nn
+  // The current derivative d^d Q lives only in the row exchange RX: each lane
+  // writes its own modes of the next derivative there and reads them back for
+  // the time integrals, so no register copy of it is kept across the loop.
   const int nn = a.step_new[cl];
   const int eflags = p.EF[elem];
   const bool need_b2 = __syncthreads_or((eflags & EF_HAS_FINER) != 0);
   const int rec_slot = p.rec_slot ? p.rec_slot[elem] : -1;
-  R de[NBX], te[NBX], t2[NBX];
+  R te[NBX], t2[NBX];
   R dm[JW][MM][6];
 #pragma unroll
-  for (int lb = 0; lb < NBX; ++lb) { de[lb] = qe[lb]; te[lb] = R(0); t2[lb] = R(0); }
+  for (int lb = 0; lb < NBX; ++lb) {
+    te[lb] = R(0);
+    t2[lb] = R(0);
+    if (lb < nb) rx[q * BS + base + lb] = qe[lb];
+  }
 #pragma unroll
   for (int jw = 0; jw < JW; ++jw)
 #pragma unroll
@@ -802,23 +809,23 @@ void k_level2(KPtrs p, LevelArgs a) {
   for (int d = 0; d < O; ++d) {
     const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
     const bool more = d + 1 < O;
-#pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) te[lb] += c_d * de[lb];
-    if (need_b2)
-#pragma unroll
-      for (int lb = 0; lb < NBX; ++lb) t2[lb] += h_d * de[lb];
-    if (rec_slot >= 0 && valid) {
-      R* rd = reinterpret_cast<R*>(p.recD) + (((size_t)rec_slot * O + d) * LPE + q) * B + base;
-#pragma unroll
-      for (int lb = 0; lb < NBX; ++lb)
-        if (lb < nb) rd[lb] = de[lb];
-    }
-    if (more) {
-#pragma unroll
-      for (int lb = 0; lb < NBX; ++lb)
-        if (lb < nb) rx[q * BS + base + lb] = de[lb];
-    }
     __syncthreads();
+    {
+      R dv[NBX];
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) dv[lb] = lb < nb ? rx[q * BS + base + lb] : R(0);
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) te[lb] += c_d * dv[lb];
+      if (need_b2)
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) t2[lb] += h_d * dv[lb];
+      if (rec_slot >= 0 && valid) {
+        R* rd = reinterpret_cast<R*>(p.recD) + (((size_t)rec_slot * O + d) * LPE + q) * B + base;
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb)
+          if (lb < nb) rd[lb] = dv[lb];
+      }
+    }
     if (more) {
       R full[B];
 #pragma unroll
@@ -870,7 +877,7 @@ void k_level2(KPtrs p, LevelArgs a) {
           if (more) {
             const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
             const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
-            de[lb] = lam * delta * div + R(2) * mu * eps + cq;
+            rx[q * BS + b] = lam * delta * div + R(2) * mu * eps + cq;
           }
         }
       }
@@ -878,10 +885,12 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
       for (int lb = 0; lb < NBX; ++lb) {
         const int b = base + lb;
-        if (lb < nb) de[lb] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+        if (lb < nb) rx[q * BS + b] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
       }
     }
   }
+  // (the barrier after the last loop's products orders every read of RX
+  // before the time integral is written there)
 
   // ------------------------------------------------ traces and volume
 #pragma unroll
