@@ -51,8 +51,13 @@ struct edg_ctx {
 
   std::vector<int> cl;  // 0-based cluster per caller element
   double dt_min = 0, lam = 1, speedup = 1;
+  // internal order: clusters finest first, each cluster's range starting on a
+  // group boundary (multiple of EPW); internal slots past a cluster's last
+  // element up to the next boundary are padding (internal_to_user = -1)
   std::vector<int64_t> internal_to_user, user_to_internal;
-  int cl_end[MAX_CLUSTERS] = {0};
+  int cl_end[MAX_CLUSTERS] = {0};    // padded end (group aligned) of cluster l
+  int cl_vend[MAX_CLUSTERS] = {0};   // end of cluster l's real elements
+  int64_t cl_count[MAX_CLUSTERS] = {0};
   double dt_cl[MAX_CLUSTERS] = {0};
   int64_t level = 0;
   int64_t nstep[MAX_CLUSTERS] = {0};
@@ -227,7 +232,11 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
   FI.assign((size_t)Kp * 8, 0);
   EF.assign((size_t)Kp, 0);
   for (int64_t ki = 0; ki < Kp; ++ki) {
-    const int64_t k = c->internal_to_user[ki < c->K ? ki : 0];
+    const int64_t k = c->internal_to_user[ki];
+    if (k < 0) {   // padding slot: no neighbours, zero parameters, never stored
+      for (int i = 0; i < 4; ++i) FI[(size_t)ki * 8 + 2 * i] = -1;
+      continue;
+    }
     R* p = &P[(size_t)ki * NPARAM];
     const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
     const double mu = rho * vs * vs, lam = rho * vp * vp - 2.0 * mu;
@@ -269,15 +278,10 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
         f[4] = R(rho * vp);
         f[5] = R(rho * vs);
       }
-      if (ki >= c->K) {  // padding: boundary faces, never written
-        nb_int = -1;
-        bc = EDG_BC_ABSORB;
-        rel = 0;
-      }
       FI[(size_t)ki * 8 + 2 * i] = nb_int;
       FI[(size_t)ki * 8 + 2 * i + 1] = j | (bc << 4) | ((rel + 1) << 8);
     }
-    EF[(size_t)ki] = ki < c->K ? flags : 0;
+    EF[(size_t)ki] = flags;
   }
 }
 
@@ -441,7 +445,8 @@ LevelArgs base_args(const edg_ctx* c) {
   std::memset(&a, 0, sizeof a);
   a.n_clusters = c->cfg.n_clusters;
   for (int l = 0; l < MAX_CLUSTERS; ++l) {
-    a.cl_end[l] = l < c->cfg.n_clusters ? c->cl_end[l] : (int)c->K;
+    a.cl_end[l] = c->cl_end[l];
+    a.cl_vend[l] = c->cl_vend[l];
     a.dt[l] = c->dt_cl[l];
     for (int d = 0; d < c->O; ++d) {
       double f = 1.0;
@@ -684,19 +689,32 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
     cluster_all(K, dt.data(), c->nbr.data(), Nc, c->cfg.lambda, c->cl, c->lam, c->speedup);
   }
   for (int l = 0; l < MAX_CLUSTERS; ++l) c->dt_cl[l] = std::ldexp(c->lam * c->dt_min, l);
-  // reorder: by cluster, then caller order
-  c->internal_to_user.resize(K);
-  std::iota(c->internal_to_user.begin(), c->internal_to_user.end(), 0);
-  std::stable_sort(c->internal_to_user.begin(), c->internal_to_user.end(),
-                   [&](int64_t a, int64_t b) { return c->cl[a] < c->cl[b]; });
+  // reorder: by cluster, then caller order; every cluster range starts on a
+  // group boundary so that a workgroup never mixes clusters
+  for (int l = 0; l < MAX_CLUSTERS; ++l) c->cl_count[l] = 0;
+  for (int64_t k = 0; k < K; ++k) c->cl_count[c->cl[k]]++;
+  int64_t start[MAX_CLUSTERS + 1];
+  start[0] = 0;
+  for (int l = 0; l < MAX_CLUSTERS; ++l) {
+    const int64_t vend = start[l] + (l < Nc ? c->cl_count[l] : 0);
+    start[l + 1] = (vend + EPW - 1) / EPW * EPW;
+    c->cl_vend[l] = (int)vend;
+    c->cl_end[l] = (int)start[l + 1];
+  }
+  c->Kp = std::max<int64_t>(start[MAX_CLUSTERS], EPW);
+  c->G = c->Kp / EPW;
+  c->internal_to_user.assign(c->Kp, -1);
   c->user_to_internal.resize(K);
-  for (int64_t ki = 0; ki < K; ++ki) c->user_to_internal[c->internal_to_user[ki]] = ki;
-  for (int l = 0; l < MAX_CLUSTERS; ++l) c->cl_end[l] = 0;
-  for (int64_t k = 0; k < K; ++k)
-    for (int l = c->cl[k]; l < MAX_CLUSTERS; ++l) c->cl_end[l]++;
+  {
+    int64_t pos[MAX_CLUSTERS];
+    for (int l = 0; l < MAX_CLUSTERS; ++l) pos[l] = start[l];
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t ki = pos[c->cl[k]]++;
+      c->internal_to_user[ki] = k;
+      c->user_to_internal[k] = ki;
+    }
+  }
   // device state
-  c->G = (K + EPW - 1) / EPW;
-  c->Kp = c->G * EPW;
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
   int rc;
   if ((rc = dev_alloc(c, c->Qe, (size_t)c->G * c->B * EPW * LPE * rs))) return rc;
@@ -860,7 +878,7 @@ int edg_advance_to(edg_ctx* c, double t) {
 
   LevelArgs a = base_args(c);
   a.kind = KIND_PREDICT;
-  a.end = (int)c->K;
+  a.end = c->cl_end[Nc - 1];
   for (int l = 0; l < Nc; ++l) a.step_new[l] = (int)c->nstep[l];
   int rc = launch_timed(c, fn, p, a, 0);
   if (rc) return rc;
@@ -873,6 +891,8 @@ int edg_advance_to(edg_ctx* c, double t) {
       if (g % ((int64_t)1 << l) == 0) lmax = l;
     a = base_args(c);
     a.end = c->cl_end[lmax];
+    int64_t upd = 0;
+    for (int l = 0; l <= lmax; ++l) upd += c->cl_count[l];
     for (int l = 0; l <= lmax; ++l) {
       a.step_fin[l] = (int)c->nstep[l];
       a.step_new[l] = (int)c->nstep[l] + 1;
@@ -880,9 +900,9 @@ int edg_advance_to(edg_ctx* c, double t) {
     if (c->n_src > 0 && (rc = fn.src(p, a, sa, c->stream)))
       return fail(c, EDG_EHIP, std::string("source kernel: ") + hipGetErrorString((hipError_t)rc));
     a.kind = j < L ? KIND_FUSED : KIND_NEIGHBOR;
-    if ((rc = launch_timed(c, fn, p, a, a.end))) return rc;
+    if ((rc = launch_timed(c, fn, p, a, upd))) return rc;
     for (int l = 0; l <= lmax; ++l) c->nstep[l]++;
-    c->updates += a.end;
+    c->updates += upd;
     if (j < L && c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->stream)))
       return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
   }

@@ -156,7 +156,8 @@ void k_level(KPtrs p, LevelArgs a) {
   const int q = e < EPW ? r : 0;
   const int g = blockIdx.x;
   const int elem = g * EPW + ec;
-  const bool valid = (e < EPW) && (elem < a.end);
+  const int cl = cluster_of(a, g * EPW);        // one cluster per workgroup (uniform)
+  const bool valid = (e < EPW) && (elem < a.cl_vend[cl]);
   const int slot = ec * LPE + q;
   R* const reg = lds + ec * L::REGION;
 
@@ -167,7 +168,6 @@ void k_level(KPtrs p, LevelArgs a) {
   const size_t Kp = (size_t)p.Kp;
   const size_t tstride = (size_t)4 * LPE * FP;   // per element in a trace slot
 
-  const int cl = cluster_of(a, elem);
   const bool is_stress = q < 6;
   int qi = 0, qj = 0;                        // stress component (i, j) of this row
   if (q < 3) { qi = q; qj = q; }
@@ -560,10 +560,13 @@ __device__ __forceinline__ int gslot(int row, int dir) {
   return dir == 0 ? 16 : (dir == 2 ? 17 : 18);
 }
 
-template <class R, int O, int M>
+// KIND is the launch kind (KIND_PREDICT, KIND_FUSED, KIND_NEIGHBOR) as a
+// template parameter: one code path per kernel keeps the register allocation
+// of the fused path free of the neighbour-only exit.
 #ifndef EDG_LEVEL2_WAVES
 #define EDG_LEVEL2_WAVES 2
 #endif
+template <class R, int O, int M, int KIND>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(EDG_LEVEL2_WAVES, 4)))
 void k_level2(KPtrs p, LevelArgs a) {
   using RF = edg_gen::Ref<O>;
@@ -583,7 +586,8 @@ void k_level2(KPtrs p, LevelArgs a) {
   const int q = e < EPW ? r : 0;
   const int g = blockIdx.x;
   const int elem = g * EPW + ec;
-  const bool valid = (e < EPW) && (elem < a.end);
+  const int cl = cluster_of(a, g * EPW);        // one cluster per workgroup (uniform)
+  const bool valid = (e < EPW) && (elem < a.cl_vend[cl]);
   const int slot = ec * LPE + q;
   const int base = w ? RF::MB1 : 0;
   const int nb = w ? NB1 : NB0;
@@ -594,14 +598,17 @@ void k_level2(KPtrs p, LevelArgs a) {
   R* const coup = reg + L::GRAD;
   R* const rx = reg + L::GRAD + L::COUP;
 
-  R* Qe = reinterpret_cast<R*>(p.Qe);
-  R* Qa = reinterpret_cast<R*>(p.Qa);
-  const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
-  const int* FI = p.FI + (size_t)elem * 8;
+  // Global addresses are a per-workgroup (uniform, scalar) base plus a 32-bit
+  // lane offset, so no 64-bit per-lane address has to stay live.
+  constexpr int TS = 4 * LPE * FP;                // trace floats per element
   const size_t Kp = (size_t)p.Kp;
-  const size_t tstride = (size_t)4 * LPE * FP;
+  const size_t tstride = (size_t)TS;
+  R* const Qg = reinterpret_cast<R*>(p.Qe) + (size_t)g * B * NSLOT;
+  R* const Qag = reinterpret_cast<R*>(p.Qa) + (size_t)g * JB * MM * 6 * NSLOT;
+  const R* P = reinterpret_cast<const R*>(p.P) + (size_t)g * EPW * NPARAM + ec * NPARAM;
+  const int* FI = p.FI + (size_t)g * EPW * 8 + ec * 8;
+  const size_t tg = (size_t)g * EPW * TS;        // this workgroup's first trace
 
-  const int cl = cluster_of(a, elem);
   const bool is_stress = q < 6;
   int qi = 0, qj = 0;
   if (q < 3) { qi = q; qj = q; }
@@ -637,14 +644,13 @@ void k_level2(KPtrs p, LevelArgs a) {
   const int d0 = gslot(6, 0) * BS, d1 = gslot(7, 1) * BS, d2 = gslot(8, 2) * BS;
 
   R qe[NBX];
-  const size_t gbase = (size_t)g * B;
 #pragma unroll
   for (int lb = 0; lb < NBX; ++lb)
-    qe[lb] = lb < nb ? Qe[(gbase + base + lb) * NSLOT + slot] : R(0);
+    qe[lb] = lb < nb ? Qg[(base + lb) * NSLOT + slot] : R(0);
 
   // ------------------------------------------------ surface: finish step n
   bool coup_pending = false;
-  if (a.kind != KIND_PREDICT) {
+  if constexpr (KIND != KIND_PREDICT) {
     const int n = a.step_fin[cl];
     const R* T1 = reinterpret_cast<const R*>(p.T1);
     const R* T2 = reinterpret_cast<const R*>(p.T2);
@@ -655,7 +661,7 @@ void k_level2(KPtrs p, LevelArgs a) {
       const int nbr = FI[2 * i];
       const int code = FI[2 * i + 1];
       const int j = code & 15, rel = ((code >> 8) & 15) - 1;
-      const R* own = T1 + ((size_t)(n & 1) * Kp + elem) * tstride + (size_t)(i * LPE + q) * FP;
+      const R* own = T1 + (size_t)(n & 1) * Kp * tstride + tg + (ec * TS + (i * LPE + q) * FP);
       R* dmn = fac + ((i * 2 + 0) * LPE + q) * FS;
       R* dpl = fac + ((i * 2 + 1) * LPE + q) * FS;
 #pragma unroll
@@ -754,7 +760,7 @@ void k_level2(KPtrs p, LevelArgs a) {
       for (int c = 0; c < 6; ++c) {
         R v = R(0);
         if (M > 0 && own) {
-          v = Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slotq];
+          v = Qag[((jb * MM + l) * 6 + c) * NSLOT + slotq];
           if (coup_pending) v += om[l] * coup[c * BS + b];
         }
         qa[jw][l][c] = v;
@@ -763,11 +769,11 @@ void k_level2(KPtrs p, LevelArgs a) {
   }
   if (M > 0 && coup_pending) __syncthreads();
 
-  if (a.kind == KIND_NEIGHBOR) {
+  if constexpr (KIND == KIND_NEIGHBOR) {
     if (valid) {
 #pragma unroll
       for (int lb = 0; lb < NBX; ++lb)
-        if (lb < nb) Qe[(gbase + base + lb) * NSLOT + slot] = qe[lb];
+        if (lb < nb) Qg[(base + lb) * NSLOT + slot] = qe[lb];
       if (M > 0)
 #pragma unroll
         for (int jw = 0; jw < JW; ++jw) {
@@ -776,7 +782,7 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
             for (int l = 0; l < MM; ++l)
 #pragma unroll
-              for (int c = 0; c < 6; ++c) Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = qa[jw][l][c];
+              for (int c = 0; c < 6; ++c) Qag[((jb * MM + l) * 6 + c) * NSLOT + slot] = qa[jw][l][c];
         }
     }
     return;
@@ -903,28 +909,26 @@ void k_level2(KPtrs p, LevelArgs a) {
     for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
     R pt[2 * FP];
     if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
-    const int el2 = fresh(elem);
-    const size_t own = ((size_t)(nn & 1) * Kp + el2) * tstride + (size_t)q * FP;
+    const int own = fresh(ec * TS + q * FP);
     if (valid) {
-      R* T1 = reinterpret_cast<R*>(p.T1);
+      R* T1 = reinterpret_cast<R*>(p.T1) + (size_t)(nn & 1) * Kp * tstride + tg;
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-        for (int f = 0; f < FP; ++f) T1[own + (size_t)(2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+        for (int f = 0; f < FP; ++f) T1[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
     }
     if ((eflags & EF_HAS_COARSER) && valid) {
-      R* T3 = reinterpret_cast<R*>(p.T3);
-      const size_t o3 = ((size_t)((nn >> 1) & 1) * Kp + el2) * tstride + (size_t)q * FP;
+      R* T3 = reinterpret_cast<R*>(p.T3) + (size_t)((nn >> 1) & 1) * Kp * tstride + tg;
       if ((nn & 1) == 0) {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T3[o3 + (size_t)(2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) T3[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
       } else {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T3[o3 + (size_t)(2 * w + ii) * LPE * FP + f] += pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) T3[own + (2 * w + ii) * LPE * FP + f] += pt[ii * FP + f];
       }
     }
     if (w == 0) RF::vol_grad_p0(full, G, gw0, gw1, gw2);
@@ -978,12 +982,12 @@ void k_level2(KPtrs p, LevelArgs a) {
     R pt[2 * FP];
     if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
     if (valid && (eflags & EF_HAS_FINER)) {
-      R* T2 = reinterpret_cast<R*>(p.T2);
-      const size_t own = ((size_t)(nn & 1) * Kp + fresh(elem)) * tstride + (size_t)q * FP;
+      R* T2 = reinterpret_cast<R*>(p.T2) + (size_t)(nn & 1) * Kp * tstride + tg;
+      const int own = fresh(ec * TS + q * FP);
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-        for (int f = 0; f < FP; ++f) T2[own + (size_t)(2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+        for (int f = 0; f < FP; ++f) T2[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
     }
   }
 
@@ -991,7 +995,7 @@ void k_level2(KPtrs p, LevelArgs a) {
     const int sl = fresh(slot);
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb)
-      if (lb < nb) Qe[(gbase + base + lb) * NSLOT + sl] = qe[lb];
+      if (lb < nb) Qg[(base + lb) * NSLOT + sl] = qe[lb];
     if (M > 0)
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
@@ -1000,7 +1004,7 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
           for (int l = 0; l < MM; ++l)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) Qa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + sl] = qa[jw][l][c];
+            for (int c = 0; c < 6; ++c) Qag[((jb * MM + l) * 6 + c) * NSLOT + sl] = qa[jw][l][c];
       }
   }
 }
@@ -1086,9 +1090,14 @@ template <class R, int O, int M>
 int launch_level(const KPtrs& p, const LevelArgs& a, hipStream_t st) {
   const int grid = (a.end + EPW - 1) / EPW;
   if (grid <= 0) return 0;
-  if constexpr (std::is_same<R, float>::value && O >= 4)
-    hipLaunchKernelGGL((k_level2<R, O, M>), dim3(grid), dim3(128), 0, st, p, a);
-  else
+  if constexpr (std::is_same<R, float>::value && O >= 4) {
+    if (a.kind == KIND_FUSED)
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_FUSED>), dim3(grid), dim3(128), 0, st, p, a);
+    else if (a.kind == KIND_PREDICT)
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_PREDICT>), dim3(grid), dim3(128), 0, st, p, a);
+    else
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_NEIGHBOR>), dim3(grid), dim3(128), 0, st, p, a);
+  } else
     hipLaunchKernelGGL((k_level<R, O, M>), dim3(grid), dim3(64), 0, st, p, a);
   return (int)hipGetLastError();
 }

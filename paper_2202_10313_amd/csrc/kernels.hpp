@@ -33,10 +33,11 @@ struct KPtrs {
 };
 
 struct LevelArgs {
-  int end;           // elements [0, end) take part (clusters are contiguous, finest first)
+  int end;           // internal slots [0, end) take part (clusters are contiguous, finest first)
   int kind;
   int n_clusters;
-  int cl_end[MAX_CLUSTERS];
+  int cl_end[MAX_CLUSTERS];     // padded end of cluster l (multiple of EPW)
+  int cl_vend[MAX_CLUSTERS];    // end of cluster l's real elements (the rest is padding)
   int step_fin[MAX_CLUSTERS];   // index of the step that ends at this level
   int step_new[MAX_CLUSTERS];   // index of the step that starts at this level
   double dt[MAX_CLUSTERS];

@@ -166,7 +166,8 @@ def test_full_size_sampled_parity():
             errs[(name, int(k))] = element_parity(q1[k], orc.Q[np.searchsorted(U, k)])
     worst = max(errs, key=errs.get)
     print(f"[fullsize] worst element {worst}: {errs[worst]:.2e}", flush=True)
-    assert errs[worst] <= TOL_FP32, errs
+    bad = {key: v for key, v in errs.items() if not v <= TOL_FP32}
+    assert not bad, f"sampled elements above {TOL_FP32}: {bad}"
     e_rec = seis_parity(seis, orc.seis)
     print(f"[fullsize] receiver parity {e_rec:.2e}", flush=True)
     assert e_rec <= TOL_FP32
