@@ -65,7 +65,7 @@ typedef struct edg_ctx edg_ctx;
 typedef struct {
   int32_t order;       /* O in 2..5 (B(O) = O(O+1)(O+2)/6 basis functions) */
   int32_t mechanisms;  /* relaxation mechanisms m: 0 (elastic) or 3 */
-  int32_t n_runs;      /* independent runs sharing the mesh: 1 */
+  int32_t n_runs;      /* independent runs sharing mesh, materials and clusters: 1..32 */
   int32_t n_clusters;  /* N_c in 1..5 */
   int32_t fp64;        /* 1: FP64 state and arithmetic, 0: FP32 */
   double cfl;          /* C in dt_k = C 2 r_k / ((2(O-1)+1) vp_k), r_k the insphere radius */
@@ -103,7 +103,10 @@ int edg_upload_materials(edg_ctx* ctx, const double* rho, const double* vp, cons
  * element order (used as given; EDG_EINVAL if two face neighbours differ by
  * more than one), or NULL to derive them from the CFL steps, the interval
  * rule, normalisation and the lambda of the configuration.  Allocates the
- * device state; the DOFs start at zero and the time at 0. */
+ * device state of all n_runs runs (per run: the DOFs, B1 of every element,
+ * B2 / B3 of the elements with a finer / coarser neighbour, each twice for
+ * the step parity); the DOFs start at zero, the time at 0, and earlier
+ * sources and receivers are dropped. */
 int edg_upload_clusters(edg_ctx* ctx, const int32_t* cluster);
 
 /* Derived clustering: cluster_out [K] (may be NULL), dt_min (smallest CFL
@@ -113,34 +116,37 @@ int edg_upload_clusters(edg_ctx* ctx, const int32_t* cluster);
 int edg_get_clusters(const edg_ctx* ctx, int32_t* cluster_out, double* dt_min, double* lambda,
                      double* sync_dt, double* speedup);
 
-/* Modal DOFs [K][Nq][B] of run `run` (0) at the current time.  Only at a
- * synchronisation point (always true between calls). */
+/* Modal DOFs [K][Nq][B] of run `run` (0..n_runs-1) at the current time.  Only
+ * at a synchronisation point (always true between calls). */
 int edg_set_initial(edg_ctx* ctx, int32_t run, const double* dofs);
 
-/* Moment-tensor point sources of run `run`: xyz [n][3], moment [n][6]
- * (xx,yy,zz,xy,yz,xz, N m), stf_params [n][2] (see EDG_STF_*).  Each source
- * adds -M phi(x_s)/|det J| times the exact integral of its moment rate over
- * each step of the element that contains it (lowest element index on ties);
- * EDG_EINVAL if a point is outside the mesh.  Replaces earlier sources. */
+/* Moment-tensor point sources of run `run` (0..n_runs-1): xyz [n][3], moment
+ * [n][6] (xx,yy,zz,xy,yz,xz, N m), stf_params [n][2] (see EDG_STF_*).  Each
+ * source adds -M phi(x_s)/|det J| times the exact integral of its moment rate
+ * over each step of the element that contains it (lowest element index on
+ * ties); EDG_EINVAL if a point is outside the mesh.  Replaces the earlier
+ * sources of that run only. */
 int edg_set_sources(edg_ctx* ctx, int32_t run, int64_t n, const double* xyz, const double* moment,
                     int32_t stf_kind, const double* stf_params);
 
-/* Receivers at xyz [n][3] sampling the 9 elastic quantities every dt_sample
- * from t = 0 (n_samples samples); each sample comes from the Taylor
- * expansion of the covering element's prediction for the step that contains
- * the sample time.  Clears recorded samples. */
+/* Receivers at xyz [n][3], the same for every run, sampling the 9 elastic
+ * quantities every dt_sample from t = 0 (n_samples samples); each sample comes
+ * from the Taylor expansion of the covering element's prediction for the step
+ * that contains the sample time.  Clears the recorded samples of all runs. */
 int edg_set_receivers(edg_ctx* ctx, int64_t n, const double* xyz, double dt_sample, int64_t n_samples);
 
-/* Advance every element to time t (a multiple of sync_dt, not earlier than
- * the current time; EDG_ENOTSYNC otherwise).  Runs on the context's stream
- * and returns after the work has been enqueued and completed. */
+/* Advance every element of every run to time t (a multiple of sync_dt, not
+ * earlier than the current time; EDG_ENOTSYNC otherwise).  Each LTS level is
+ * one launch for all runs (grid = element groups x runs).  Runs on the
+ * context's stream and returns after the work has completed. */
 int edg_advance_to(edg_ctx* ctx, double t);
 
-/* Recorded seismograms of run `run`: out [n_rec][n_samples][9]; cap = number
- * of doubles available (EDG_ECAP if smaller). */
+/* Recorded seismograms of run `run` (0..n_runs-1): out [n_rec][n_samples][9];
+ * cap = number of doubles available (EDG_ECAP if smaller). */
 int edg_read_receivers(edg_ctx* ctx, int32_t run, double* out, int64_t cap);
 
-/* DOFs [K][Nq][B] of run `run` at the current time; cap = doubles available. */
+/* DOFs [K][Nq][B] of run `run` (0..n_runs-1) at the current time; cap = doubles
+ * available. */
 int edg_read_dofs(edg_ctx* ctx, int32_t run, double* out, int64_t cap);
 
 /* Current simulation time (0 for a NULL context). */
@@ -156,7 +162,7 @@ const char* edg_last_error(const edg_ctx* ctx);
 int edg_enable_timing(edg_ctx* ctx, int32_t enable);
 int edg_kernel_stats(const edg_ctx* ctx, int64_t* launches, double* total_ms, int64_t* element_updates);
 
-/* Element updates (element x own step) performed so far. */
+/* Element updates (element x own step x run) performed so far. */
 int64_t edg_element_updates(const edg_ctx* ctx);
 
 /* Destroy the context and free its device memory (NULL is ignored). */

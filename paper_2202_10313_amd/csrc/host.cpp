@@ -64,10 +64,20 @@ struct edg_ctx {
   int64_t updates = 0;
 
   int64_t G = 0, Kp = 0;
-  DevBuf Qe, Qa, P, FI, EF, T1, T2, T3, RecSlot, RecD;
-  // sources
+  int runs = 1;                     // independent runs sharing the mesh
+  int64_t N2 = 1, N3 = 1;           // B2 / B3 slots (elements with a finer / coarser neighbour)
+  size_t run_qe = 0, run_qa = 0, run_t1 = 0, run_t2 = 0, run_t3 = 0, run_recd = 0;   // words per run
+  std::vector<int> FI_host;         // [Kp][FI_WORDS]
+  DevBuf Qe, Qa, P, FI, T1, T2, T3, RecD;
+  // sources, per run
+  struct Source {
+    int elem, kind;
+    double par[2], moment[6], idet;
+    std::vector<double> phi;
+  };
+  std::vector<std::vector<Source>> src_of_run;
   int n_src = 0;
-  DevBuf s_elem, s_kind, s_par, s_mom, s_phi, s_idet;
+  DevBuf s_run, s_elem, s_kind, s_par, s_mom, s_phi, s_idet;
   // receivers
   int n_rec = 0;
   int64_t rec_ns = 0;
@@ -226,15 +236,36 @@ void cluster_all(int64_t K, const double* dt, const int64_t* nbr, int Nc, double
 }
 
 template <class R>
-void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vector<int>& EF) {
+void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI) {
   const int64_t Kp = c->Kp;
   P.assign((size_t)Kp * NPARAM, R(0));
-  FI.assign((size_t)Kp * 8, 0);
-  EF.assign((size_t)Kp, 0);
+  FI.assign((size_t)Kp * FI_WORDS, 0);
+  // flags and compact B2 / B3 slots of every element (internal order)
+  std::vector<int> flags(Kp, 0), s2(Kp, -1), s3(Kp, -1);
+  int64_t n2 = 0, n3 = 0;
   for (int64_t ki = 0; ki < Kp; ++ki) {
     const int64_t k = c->internal_to_user[ki];
+    if (k < 0) continue;
+    for (int i = 0; i < 4; ++i) {
+      const int64_t n = c->nbr[k * 4 + i];
+      if (n < 0) continue;
+      if (c->cl[n] < c->cl[k]) flags[ki] |= EF_HAS_FINER;
+      if (c->cl[n] > c->cl[k]) flags[ki] |= EF_HAS_COARSER;
+    }
+    if (flags[ki] & EF_HAS_FINER) s2[ki] = (int)n2++;
+    if (flags[ki] & EF_HAS_COARSER) s3[ki] = (int)n3++;
+  }
+  c->N2 = std::max<int64_t>(n2, 1);
+  c->N3 = std::max<int64_t>(n3, 1);
+  for (int64_t ki = 0; ki < Kp; ++ki) {
+    int* fi = &FI[(size_t)ki * FI_WORDS];
+    const int64_t k = c->internal_to_user[ki];
+    fi[12] = flags[ki];
+    fi[13] = s2[ki];
+    fi[14] = s3[ki];
+    fi[15] = -1;
     if (k < 0) {   // padding slot: no neighbours, zero parameters, never stored
-      for (int i = 0; i < 4; ++i) FI[(size_t)ki * 8 + 2 * i] = -1;
+      for (int i = 0; i < 4; ++i) fi[3 * i] = -1;
       continue;
     }
     R* p = &P[(size_t)ki * NPARAM];
@@ -244,9 +275,9 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
     const double* G = &c->Gm[(size_t)k * 9];
     for (int kk = 0; kk < 3; ++kk)
       for (int d = 0; d < 3; ++d) {
-        double s = 0.0;
-        for (int cc = 0; cc < 3; ++cc) s += c->dirs.Vinv[cc * 3 + kk] * G[cc * 3 + d];
-        p[kk * 3 + d] = R(s);
+        double sum = 0.0;
+        for (int cc = 0; cc < 3; ++cc) sum += c->dirs.Vinv[cc * 3 + kk] * G[cc * 3 + d];
+        p[kk * 3 + d] = R(sum);
       }
     p[9] = R(1.0 / rho);
     p[10] = R(lam);
@@ -258,13 +289,12 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
       p[14 + 2 * l] = R((lam + 2.0 * mu) * ypl - 2.0 * mu * ysl);
       p[15 + 2 * l] = R(2.0 * mu * ysl);
     }
-    int flags = 0;
     for (int i = 0; i < 4; ++i) {
       R* f = p + 20 + 6 * i;
       for (int d = 0; d < 3; ++d) f[d] = R(c->normals[(k * 4 + i) * 3 + d]);
       f[3] = R(2.0 * c->areas[k * 4 + i] / c->absdet[k]);
       const int64_t n = c->nbr[k * 4 + i];
-      int nb_int = -1, j = 0, rel = 0, bc = c->bc[k * 4 + i];
+      int nb_int = -1, j = 0, rel = 0, bc = c->bc[k * 4 + i], aux = 0;
       if (n >= 0) {
         f[4] = R(c->rho[n] * c->vp[n]);
         f[5] = R(c->rho[n] * c->vs[n]);
@@ -272,16 +302,16 @@ void pack_tables(edg_ctx* c, std::vector<R>& P, std::vector<int>& FI, std::vecto
         j = (int)c->nbr_face[k * 4 + i];
         rel = c->cl[n] - c->cl[k];
         bc = 0;
-        if (rel < 0) flags |= EF_HAS_FINER;
-        if (rel > 0) flags |= EF_HAS_COARSER;
+        if (rel > 0) aux = s2[nb_int];   // the coarser neighbour's B2
+        if (rel < 0) aux = s3[nb_int];   // the finer neighbour's B3
       } else {
         f[4] = R(rho * vp);
         f[5] = R(rho * vs);
       }
-      FI[(size_t)ki * 8 + 2 * i] = nb_int;
-      FI[(size_t)ki * 8 + 2 * i + 1] = j | (bc << 4) | ((rel + 1) << 8);
+      fi[3 * i] = nb_int;
+      fi[3 * i + 1] = j | (bc << 4) | ((rel + 1) << 8);
+      fi[3 * i + 2] = aux;
     }
-    EF[(size_t)ki] = flags;
   }
 }
 
@@ -301,7 +331,7 @@ inline size_t qa_size(const edg_ctx* c) {
 }
 
 template <class R>
-int set_dofs_t(edg_ctx* c, const double* dofs) {
+int set_dofs_t(edg_ctx* c, int run, const double* dofs) {
   const int B = c->B, NQ = c->NQ;
   std::vector<R> he((size_t)c->G * B * EPW * LPE, R(0));
   std::vector<R> ha(qa_size(c), R(0));
@@ -325,18 +355,20 @@ int set_dofs_t(edg_ctx* c, const double* dofs) {
       }
     }
   }
-  HIPCHK(c, hipMemcpy(c->Qe.p, he.data(), he.size() * sizeof(R), hipMemcpyHostToDevice));
-  if (c->M > 0) HIPCHK(c, hipMemcpy(c->Qa.p, ha.data(), ha.size() * sizeof(R), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy((R*)c->Qe.p + run * c->run_qe, he.data(), he.size() * sizeof(R), hipMemcpyHostToDevice));
+  if (c->M > 0)
+    HIPCHK(c, hipMemcpy((R*)c->Qa.p + run * c->run_qa, ha.data(), ha.size() * sizeof(R), hipMemcpyHostToDevice));
   return 0;
 }
 
 template <class R>
-int get_dofs_t(edg_ctx* c, double* out) {
+int get_dofs_t(edg_ctx* c, int run, double* out) {
   const int B = c->B, NQ = c->NQ;
   std::vector<R> he((size_t)c->G * B * EPW * LPE);
   std::vector<R> ha(qa_size(c));
-  HIPCHK(c, hipMemcpy(he.data(), c->Qe.p, he.size() * sizeof(R), hipMemcpyDeviceToHost));
-  if (c->M > 0) HIPCHK(c, hipMemcpy(ha.data(), c->Qa.p, ha.size() * sizeof(R), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(he.data(), (R*)c->Qe.p + run * c->run_qe, he.size() * sizeof(R), hipMemcpyDeviceToHost));
+  if (c->M > 0)
+    HIPCHK(c, hipMemcpy(ha.data(), (R*)c->Qa.p + run * c->run_qa, ha.size() * sizeof(R), hipMemcpyDeviceToHost));
   std::vector<double> row(B);
   for (int64_t k = 0; k < c->K; ++k) {
     const int64_t ki = c->user_to_internal[k];
@@ -392,18 +424,20 @@ int64_t locate(const edg_ctx* c, const double* x, double xi_sorted[3]) {
 
 template <class R, int O, int M>
 struct Launch {
-  static int level(const KPtrs& p, const LevelArgs& a, hipStream_t s) { return launch_level<R, O, M>(p, a, s); }
+  static int level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t s) {
+    return launch_level<R, O, M>(p, a, runs, s);
+  }
   static int src(const KPtrs& p, const LevelArgs& a, const SrcArgs& sa, hipStream_t s) {
     return launch_sources<R, O, M>(p, a, sa, s);
   }
-  static int rec(const KPtrs& p, const LevelArgs& a, const RecArgs& ra, hipStream_t s) {
-    return launch_receivers<R, O, M>(p, a, ra, s);
+  static int rec(const KPtrs& p, const LevelArgs& a, const RecArgs& ra, int runs, hipStream_t s) {
+    return launch_receivers<R, O, M>(p, a, ra, runs, s);
   }
 };
 
-typedef int (*LevelFn)(const KPtrs&, const LevelArgs&, hipStream_t);
+typedef int (*LevelFn)(const KPtrs&, const LevelArgs&, int, hipStream_t);
 typedef int (*SrcFn)(const KPtrs&, const LevelArgs&, const SrcArgs&, hipStream_t);
-typedef int (*RecFn)(const KPtrs&, const LevelArgs&, const RecArgs&, hipStream_t);
+typedef int (*RecFn)(const KPtrs&, const LevelArgs&, const RecArgs&, int, hipStream_t);
 
 struct Fns {
   LevelFn level = nullptr;
@@ -430,13 +464,19 @@ KPtrs kptrs(const edg_ctx* c) {
   p.Qa = c->Qa.p;
   p.P = c->P.p;
   p.FI = (const int*)c->FI.p;
-  p.EF = (const int*)c->EF.p;
   p.T1 = c->T1.p;
   p.T2 = c->T2.p;
   p.T3 = c->T3.p;
-  p.rec_slot = (const int*)c->RecSlot.p;
   p.recD = c->RecD.p;
   p.Kp = c->Kp;
+  p.N2 = c->N2;
+  p.N3 = c->N3;
+  p.run_qe = (long long)c->run_qe;
+  p.run_qa = (long long)c->run_qa;
+  p.run_t1 = (long long)c->run_t1;
+  p.run_t2 = (long long)c->run_t2;
+  p.run_t3 = (long long)c->run_t3;
+  p.run_recd = (long long)c->run_recd;
   return p;
 }
 
@@ -470,12 +510,12 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
     auto& ev = c->ev_pool[c->ev_used++];
     c->ev_updates.push_back(upd);
     HIPCHK(c, hipEventRecord(ev.first, c->stream));
-    int rc = fn.level(p, a, c->stream);
+    int rc = fn.level(p, a, c->runs, c->stream);
     if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
     HIPCHK(c, hipEventRecord(ev.second, c->stream));
     return 0;
   }
-  int rc = fn.level(p, a, c->stream);
+  int rc = fn.level(p, a, c->runs, c->stream);
   if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return 0;
 }
@@ -483,7 +523,7 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
 }  // namespace
 
 edg_ctx::~edg_ctx() {
-  for (DevBuf* b : {&Qe, &Qa, &P, &FI, &EF, &T1, &T2, &T3, &RecSlot, &RecD, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
+  for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
                     &s_idet, &r_elem, &r_slot, &r_phi, &r_out})
     dev_free(*b);
   for (auto& e : ev_pool) {
@@ -501,7 +541,7 @@ int edg_create(const edg_config* cfg, edg_ctx** out) {
   if (!cfg) return EDG_EINVAL;
   if (cfg->order < 2 || cfg->order > MAX_ORDER) return EDG_EINVAL;
   if (!(cfg->mechanisms == 0 || cfg->mechanisms == 3)) return EDG_EINVAL;
-  if (cfg->n_runs != 1) return EDG_EINVAL;
+  if (cfg->n_runs < 1 || cfg->n_runs > MAX_RUNS) return EDG_EINVAL;
   if (cfg->n_clusters < 1 || cfg->n_clusters > MAX_CLUSTERS) return EDG_EINVAL;
   if (!(cfg->cfl > 0) || cfg->lambda > 1.0 || (cfg->lambda > 0 && cfg->lambda <= 0.5)) return EDG_EINVAL;
   if (!pick(cfg->fp64, cfg->order, cfg->mechanisms).level) return EDG_EINVAL;
@@ -516,6 +556,8 @@ int edg_create(const edg_config* cfg, edg_ctx** out) {
   c->M = cfg->mechanisms;
   c->NQ = 9 + 6 * c->M;
   c->dirs = edg::sparse_directions(c->O);
+  c->runs = cfg->n_runs;
+  c->src_of_run.assign(c->runs, {});
   if (cfg->hip_stream) {
     c->stream = (hipStream_t)cfg->hip_stream;
   } else {
@@ -649,13 +691,13 @@ int edg_upload_materials(edg_ctx* c, const double* rho, const double* vp, const 
   if (c->have_clusters) {  // re-derive operators, keep clusters and state
     if (c->cfg.fp64) {
       std::vector<double> P;
-      std::vector<int> FI, EF;
-      pack_tables<double>(c, P, FI, EF);
+      std::vector<int> FI;   // unchanged by materials (the device copy keeps the receiver slots)
+      pack_tables<double>(c, P, FI);
       HIPCHK(c, hipMemcpy(c->P.p, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice));
     } else {
       std::vector<float> P;
-      std::vector<int> FI, EF;
-      pack_tables<float>(c, P, FI, EF);
+      std::vector<int> FI;
+      pack_tables<float>(c, P, FI);
       HIPCHK(c, hipMemcpy(c->P.p, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice));
     }
   }
@@ -714,34 +756,39 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
       c->user_to_internal[k] = ki;
     }
   }
-  // device state
+  // device state: tables shared by the runs, then every run's state
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
   int rc;
-  if ((rc = dev_alloc(c, c->Qe, (size_t)c->G * c->B * EPW * LPE * rs))) return rc;
-  if ((rc = dev_alloc(c, c->Qa, qa_size(c) * rs))) return rc;
-  const size_t tb = (size_t)2 * c->Kp * 4 * LPE * c->FP * rs;
-  if ((rc = dev_alloc(c, c->T1, tb))) return rc;
-  if ((rc = dev_alloc(c, c->T2, tb))) return rc;
-  if ((rc = dev_alloc(c, c->T3, tb))) return rc;
-  HIPCHK(c, hipMemset(c->Qe.p, 0, c->Qe.bytes));
-  HIPCHK(c, hipMemset(c->Qa.p, 0, c->Qa.bytes));
-  HIPCHK(c, hipMemset(c->T1.p, 0, tb));
-  HIPCHK(c, hipMemset(c->T2.p, 0, tb));
-  HIPCHK(c, hipMemset(c->T3.p, 0, tb));
-  std::vector<int> FI, EF;
   if (c->cfg.fp64) {
     std::vector<double> P;
-    pack_tables<double>(c, P, FI, EF);
+    pack_tables<double>(c, P, c->FI_host);
     if ((rc = dev_upload(c, c->P, P.data(), P.size() * sizeof(double)))) return rc;
   } else {
     std::vector<float> P;
-    pack_tables<float>(c, P, FI, EF);
+    pack_tables<float>(c, P, c->FI_host);
     if ((rc = dev_upload(c, c->P, P.data(), P.size() * sizeof(float)))) return rc;
   }
-  if ((rc = dev_upload(c, c->FI, FI.data(), FI.size() * sizeof(int)))) return rc;
-  if ((rc = dev_upload(c, c->EF, EF.data(), EF.size() * sizeof(int)))) return rc;
-  std::vector<int> rs_slot((size_t)c->Kp, -1);
-  if ((rc = dev_upload(c, c->RecSlot, rs_slot.data(), rs_slot.size() * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->FI, c->FI_host.data(), c->FI_host.size() * sizeof(int)))) return rc;
+  const size_t ts = (size_t)4 * LPE * c->FP;   // trace words per element
+  c->run_qe = (size_t)c->G * c->B * EPW * LPE;
+  c->run_qa = c->M > 0 ? qa_size(c) : 0;
+  c->run_t1 = 2 * (size_t)c->Kp * ts;
+  c->run_t2 = 2 * (size_t)c->N2 * ts;
+  c->run_t3 = 2 * (size_t)c->N3 * ts;
+  const size_t R_ = (size_t)c->runs;
+  if ((rc = dev_alloc(c, c->Qe, R_ * c->run_qe * rs))) return rc;
+  if ((rc = dev_alloc(c, c->Qa, std::max<size_t>(R_ * c->run_qa, 1) * rs))) return rc;
+  if ((rc = dev_alloc(c, c->T1, R_ * c->run_t1 * rs))) return rc;
+  if ((rc = dev_alloc(c, c->T2, R_ * c->run_t2 * rs))) return rc;
+  if ((rc = dev_alloc(c, c->T3, R_ * c->run_t3 * rs))) return rc;
+  HIPCHK(c, hipMemset(c->Qe.p, 0, c->Qe.bytes));
+  HIPCHK(c, hipMemset(c->Qa.p, 0, c->Qa.bytes));
+  HIPCHK(c, hipMemset(c->T1.p, 0, c->T1.bytes));
+  HIPCHK(c, hipMemset(c->T2.p, 0, c->T2.bytes));
+  HIPCHK(c, hipMemset(c->T3.p, 0, c->T3.bytes));
+  c->n_rec = 0;
+  c->n_src = 0;
+  for (auto& v : c->src_of_run) v.clear();
   c->level = 0;
   for (int l = 0; l < MAX_CLUSTERS; ++l) c->nstep[l] = 0;
   c->updates = 0;
@@ -764,46 +811,67 @@ int edg_get_clusters(const edg_ctx* c, int32_t* cl_out, double* dt_min, double* 
 int edg_set_initial(edg_ctx* c, int32_t run, const double* dofs) {
   if (!c) return EDG_EINVAL;
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
-  if (run != 0 || !dofs) return fail(c, EDG_EINVAL, "bad run or null dofs");
+  if (run < 0 || run >= c->runs || !dofs) return fail(c, EDG_EINVAL, "bad run or null dofs");
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  return c->cfg.fp64 ? set_dofs_t<double>(c, dofs) : set_dofs_t<float>(c, dofs);
+  return c->cfg.fp64 ? set_dofs_t<double>(c, run, dofs) : set_dofs_t<float>(c, run, dofs);
 }
 
 int edg_read_dofs(edg_ctx* c, int32_t run, double* out, int64_t cap) {
   if (!c) return EDG_EINVAL;
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
-  if (run != 0 || !out) return fail(c, EDG_EINVAL, "bad run or null output");
+  if (run < 0 || run >= c->runs || !out) return fail(c, EDG_EINVAL, "bad run or null output");
   if (cap < c->K * c->NQ * c->B) return fail(c, EDG_ECAP, "output capacity too small");
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  return c->cfg.fp64 ? get_dofs_t<double>(c, out) : get_dofs_t<float>(c, out);
+  return c->cfg.fp64 ? get_dofs_t<double>(c, run, out) : get_dofs_t<float>(c, run, out);
 }
 
 int edg_set_sources(edg_ctx* c, int32_t run, int64_t n, const double* xyz, const double* moment, int32_t kind,
                     const double* par) {
   if (!c) return EDG_EINVAL;
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
-  if (run != 0 || n < 0 || (n > 0 && (!xyz || !moment || !par))) return fail(c, EDG_EINVAL, "bad source arguments");
+  if (run < 0 || run >= c->runs || n < 0 || (n > 0 && (!xyz || !moment || !par)))
+    return fail(c, EDG_EINVAL, "bad source arguments");
   if (kind != EDG_STF_RICKER && kind != EDG_STF_HANN) return fail(c, EDG_EINVAL, "unknown source time function");
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  std::vector<int> el(n), kd(n, kind);
-  std::vector<double> phi((size_t)n * c->B), idet(n);
+  std::vector<edg_ctx::Source> list;
   for (int64_t s = 0; s < n; ++s) {
     double xi[3];
     const int64_t k = locate(c, xyz + 3 * s, xi);
     if (k < 0) return fail(c, EDG_EINVAL, "source " + std::to_string(s) + " is outside the mesh");
-    el[s] = (int)c->user_to_internal[k];
-    auto v = eval_basis(c->O, xi);
-    std::copy(v.begin(), v.end(), phi.begin() + s * c->B);
-    idet[s] = 1.0 / c->absdet[k];
+    edg_ctx::Source src;
+    src.elem = (int)c->user_to_internal[k];
+    src.kind = kind;
+    src.par[0] = par[2 * s];
+    src.par[1] = par[2 * s + 1];
+    for (int m = 0; m < 6; ++m) src.moment[m] = moment[6 * s + m];
+    src.idet = 1.0 / c->absdet[k];
+    src.phi = eval_basis(c->O, xi);
+    list.push_back(std::move(src));
   }
+  c->src_of_run[run] = std::move(list);
+  // the device list holds the sources of every run
+  std::vector<int> rn, el, kd;
+  std::vector<double> pr, mo, phi, idet;
+  for (int r = 0; r < c->runs; ++r)
+    for (const auto& src : c->src_of_run[r]) {
+      rn.push_back(r);
+      el.push_back(src.elem);
+      kd.push_back(src.kind);
+      pr.insert(pr.end(), src.par, src.par + 2);
+      mo.insert(mo.end(), src.moment, src.moment + 6);
+      phi.insert(phi.end(), src.phi.begin(), src.phi.end());
+      idet.push_back(src.idet);
+    }
+  const size_t ns = rn.size();
   int rc;
-  if ((rc = dev_upload(c, c->s_elem, el.data(), n * sizeof(int)))) return rc;
-  if ((rc = dev_upload(c, c->s_kind, kd.data(), n * sizeof(int)))) return rc;
-  if ((rc = dev_upload(c, c->s_par, par, n * 2 * sizeof(double)))) return rc;
-  if ((rc = dev_upload(c, c->s_mom, moment, n * 6 * sizeof(double)))) return rc;
+  if ((rc = dev_upload(c, c->s_run, rn.data(), ns * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->s_elem, el.data(), ns * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->s_kind, kd.data(), ns * sizeof(int)))) return rc;
+  if ((rc = dev_upload(c, c->s_par, pr.data(), pr.size() * sizeof(double)))) return rc;
+  if ((rc = dev_upload(c, c->s_mom, mo.data(), mo.size() * sizeof(double)))) return rc;
   if ((rc = dev_upload(c, c->s_phi, phi.data(), phi.size() * sizeof(double)))) return rc;
-  if ((rc = dev_upload(c, c->s_idet, idet.data(), n * sizeof(double)))) return rc;
-  c->n_src = (int)n;
+  if ((rc = dev_upload(c, c->s_idet, idet.data(), ns * sizeof(double)))) return rc;
+  c->n_src = (int)ns;
   return EDG_OK;
 }
 
@@ -812,7 +880,7 @@ int edg_set_receivers(edg_ctx* c, int64_t n, const double* xyz, double dt_sample
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
   if (n < 0 || (n > 0 && (!xyz || !(dt_sample > 0) || ns <= 0))) return fail(c, EDG_EINVAL, "bad receiver arguments");
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  std::vector<int> el(n), slot(n), rs_slot((size_t)c->Kp, -1);
+  std::vector<int> el(n), slot(n), rs_slot((size_t)c->Kp, -1);   // receiver slot per element
   std::vector<double> phi((size_t)n * c->B);
   int nslots = 0;
   for (int64_t r = 0; r < n; ++r) {
@@ -827,13 +895,16 @@ int edg_set_receivers(edg_ctx* c, int64_t n, const double* xyz, double dt_sample
     std::copy(v.begin(), v.end(), phi.begin() + r * c->B);
   }
   int rc;
-  if ((rc = dev_upload(c, c->RecSlot, rs_slot.data(), rs_slot.size() * sizeof(int)))) return rc;
+  for (int64_t ki = 0; ki < c->Kp; ++ki) c->FI_host[(size_t)ki * FI_WORDS + 15] = rs_slot[ki];
+  if ((rc = dev_upload(c, c->FI, c->FI_host.data(), c->FI_host.size() * sizeof(int)))) return rc;
   const size_t rsz = c->cfg.fp64 ? sizeof(double) : sizeof(float);
-  if ((rc = dev_alloc(c, c->RecD, (size_t)std::max(nslots, 1) * c->O * LPE * c->B * rsz))) return rc;
+  c->run_recd = (size_t)std::max(nslots, 1) * c->O * LPE * c->B;
+  if ((rc = dev_alloc(c, c->RecD, (size_t)c->runs * c->run_recd * rsz))) return rc;
   if ((rc = dev_upload(c, c->r_elem, el.data(), n * sizeof(int)))) return rc;
   if ((rc = dev_upload(c, c->r_slot, slot.data(), n * sizeof(int)))) return rc;
   if ((rc = dev_upload(c, c->r_phi, phi.data(), phi.size() * sizeof(double)))) return rc;
-  if ((rc = dev_alloc(c, c->r_out, (size_t)std::max<int64_t>(n, 1) * ns * LPE * sizeof(double)))) return rc;
+  if ((rc = dev_alloc(c, c->r_out, (size_t)c->runs * std::max<int64_t>(n, 1) * ns * LPE * sizeof(double))))
+    return rc;
   HIPCHK(c, hipMemset(c->r_out.p, 0, c->r_out.bytes));
   c->n_rec = (int)n;
   c->rec_ns = ns;
@@ -859,6 +930,7 @@ int edg_advance_to(edg_ctx* c, double t) {
   const KPtrs p = kptrs(c);
   SrcArgs sa;
   sa.n = c->n_src;
+  sa.run = (const int*)c->s_run.p;
   sa.elem = (const int*)c->s_elem.p;
   sa.kind = (const int*)c->s_kind.p;
   sa.par = (const double*)c->s_par.p;
@@ -872,6 +944,7 @@ int edg_advance_to(edg_ctx* c, double t) {
   ra.phi = (const double*)c->r_phi.p;
   ra.dt_sample = c->rec_dt;
   ra.ns = c->rec_ns;
+  ra.run0 = 0;
   ra.out = (double*)c->r_out.p;
   c->ev_used = 0;
   c->ev_updates.clear();
@@ -882,7 +955,7 @@ int edg_advance_to(edg_ctx* c, double t) {
   for (int l = 0; l < Nc; ++l) a.step_new[l] = (int)c->nstep[l];
   int rc = launch_timed(c, fn, p, a, 0);
   if (rc) return rc;
-  if (c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->stream)))
+  if (c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->runs, c->stream)))
     return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
   for (int64_t j = 1; j <= L; ++j) {
     const int64_t g = c->level + j;
@@ -892,7 +965,7 @@ int edg_advance_to(edg_ctx* c, double t) {
     a = base_args(c);
     a.end = c->cl_end[lmax];
     int64_t upd = 0;
-    for (int l = 0; l <= lmax; ++l) upd += c->cl_count[l];
+    for (int l = 0; l <= lmax; ++l) upd += c->cl_count[l] * c->runs;
     for (int l = 0; l <= lmax; ++l) {
       a.step_fin[l] = (int)c->nstep[l];
       a.step_new[l] = (int)c->nstep[l] + 1;
@@ -903,7 +976,7 @@ int edg_advance_to(edg_ctx* c, double t) {
     if ((rc = launch_timed(c, fn, p, a, upd))) return rc;
     for (int l = 0; l <= lmax; ++l) c->nstep[l]++;
     c->updates += upd;
-    if (j < L && c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->stream)))
+    if (j < L && c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->runs, c->stream)))
       return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
   }
   c->level += L;
@@ -922,12 +995,12 @@ int edg_advance_to(edg_ctx* c, double t) {
 
 int edg_read_receivers(edg_ctx* c, int32_t run, double* out, int64_t cap) {
   if (!c) return EDG_EINVAL;
-  if (run != 0 || !out) return fail(c, EDG_EINVAL, "bad run or null output");
+  if (run < 0 || run >= c->runs || !out) return fail(c, EDG_EINVAL, "bad run or null output");
   const int64_t need = (int64_t)c->n_rec * c->rec_ns * LPE;
   if (cap < need) return fail(c, EDG_ECAP, "output capacity too small");
   if (need == 0) return EDG_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  HIPCHK(c, hipMemcpy(out, c->r_out.p, need * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(out, (double*)c->r_out.p + (size_t)run * need, need * sizeof(double), hipMemcpyDeviceToHost));
   return EDG_OK;
 }
 

@@ -140,6 +140,17 @@ __device__ __forceinline__ void godunov(const R* qm, const R* qp, R nx, R ny, R 
   out[14] = hs * (nx * vz + nz * vx);
 }
 
+// State arrays are stacked run after run: the pointers of one run.
+template <class R>
+__device__ __forceinline__ void select_run(KPtrs& p, int run) {
+  p.Qe = reinterpret_cast<R*>(p.Qe) + (size_t)run * p.run_qe;
+  p.Qa = reinterpret_cast<R*>(p.Qa) + (size_t)run * p.run_qa;
+  p.T1 = reinterpret_cast<R*>(p.T1) + (size_t)run * p.run_t1;
+  p.T2 = reinterpret_cast<R*>(p.T2) + (size_t)run * p.run_t2;
+  p.T3 = reinterpret_cast<R*>(p.T3) + (size_t)run * p.run_t3;
+  p.recD = reinterpret_cast<R*>(p.recD) + (size_t)run * p.run_recd;
+}
+
 template <class R, int O, int M>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_level(KPtrs p, LevelArgs a) {
@@ -154,6 +165,7 @@ void k_level(KPtrs p, LevelArgs a) {
   const int e = lane / LPE, r = lane % LPE;
   const int ec = e < EPW ? e : EPW - 1;     // lane 63 duplicates lane 54 (same element, same row)
   const int q = e < EPW ? r : 0;
+  select_run<R>(p, a.run0 + (int)blockIdx.y);
   const int g = blockIdx.x;
   const int elem = g * EPW + ec;
   const int cl = cluster_of(a, g * EPW);        // one cluster per workgroup (uniform)
@@ -164,7 +176,7 @@ void k_level(KPtrs p, LevelArgs a) {
   R* Qe = reinterpret_cast<R*>(p.Qe);
   R* Qa = reinterpret_cast<R*>(p.Qa);
   const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
-  const int* FI = p.FI + (size_t)elem * 8;
+  const int* FI = p.FI + (size_t)elem * FI_WORDS;
   const size_t Kp = (size_t)p.Kp;
   const size_t tstride = (size_t)4 * LPE * FP;   // per element in a trace slot
 
@@ -221,8 +233,9 @@ void k_level(KPtrs p, LevelArgs a) {
     const R* T3 = reinterpret_cast<const R*>(p.T3);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int nb = FI[2 * i];
-      const int code = FI[2 * i + 1];
+      const int nb = FI[3 * i];
+      const int code = FI[3 * i + 1];
+      const size_t aux = (size_t)FI[3 * i + 2];
       const int j = code & 15, rel = ((code >> 8) & 15) - 1;
       const R* own = T1 + ((size_t)(n & 1) * Kp + elem) * tstride + (size_t)(i * LPE + q) * FP;
       R* dmn = reg + ((i * 2 + 0) * LPE + q) * FP;
@@ -236,12 +249,12 @@ void k_level(KPtrs p, LevelArgs a) {
 #pragma unroll
           for (int f = 0; f < FP; ++f) dpl[f] = s[f];
         } else if (rel < 0) {       // finer neighbour: its accumulated B3
-          const R* s = T3 + (size_t)(n & 1) * Kp * tstride + nbo;
+          const R* s = T3 + ((size_t)(n & 1) * p.N3 + aux) * tstride + (size_t)(j * LPE + q) * FP;
 #pragma unroll
           for (int f = 0; f < FP; ++f) dpl[f] = s[f];
         } else {                    // coarser neighbour: B2, then B1 - B2
           const int c = (n >> 1) & 1;
-          const R* s2 = T2 + (size_t)c * Kp * tstride + nbo;
+          const R* s2 = T2 + ((size_t)c * p.N2 + aux) * tstride + (size_t)(j * LPE + q) * FP;
           if ((n & 1) == 0) {
 #pragma unroll
             for (int f = 0; f < FP; ++f) dpl[f] = s2[f];
@@ -263,7 +276,7 @@ void k_level(KPtrs p, LevelArgs a) {
       const int t = q + LPE * rr;
       if (t < 4 * F) {
         const int i = t / F, f = t % F;
-        const int code = FI[2 * i + 1];
+        const int code = FI[3 * i + 1];
         const int bc = (code >> 4) & 15;
         const R* fp = P + 20 + 6 * i;
         R qm[9], qp[9], out[15];
@@ -342,9 +355,9 @@ void k_level(KPtrs p, LevelArgs a) {
 
   // ------------------------------------------------ time kernel: predict step nn
   const int nn = a.step_new[cl];
-  const int eflags = p.EF[elem];
+  const int eflags = FI[12];
   const bool need_b2 = __any((eflags & EF_HAS_FINER) != 0);
-  const int rec_slot = p.rec_slot ? p.rec_slot[elem] : -1;
+  const int rec_slot = FI[15];
   R de[B], te[B], t2[B];
   R dm[JB][MM][6];
 #pragma unroll
@@ -440,7 +453,7 @@ void k_level(KPtrs p, LevelArgs a) {
     }
     if (eflags & EF_HAS_COARSER) {     // B3: restart on even steps, accumulate on odd
       R* T3 = reinterpret_cast<R*>(p.T3);
-      const size_t o3 = ((size_t)((nn >> 1) & 1) * Kp + elem) * tstride + (size_t)q * FP;
+      const size_t o3 = ((size_t)((nn >> 1) & 1) * p.N3 + (size_t)FI[14]) * tstride + (size_t)q * FP;
       if (valid) {
         if ((nn & 1) == 0) {
 #pragma unroll
@@ -459,10 +472,11 @@ void k_level(KPtrs p, LevelArgs a) {
       RF::trace(t2, pt);
       if (valid && (eflags & EF_HAS_FINER)) {
         R* T2 = reinterpret_cast<R*>(p.T2);
+        const size_t o2 = ((size_t)(nn & 1) * p.N2 + (size_t)FI[13]) * tstride + (size_t)q * FP;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T2[own + (size_t)i * LPE * FP + f] = pt[i * FP + f];
+          for (int f = 0; f < FP; ++f) T2[o2 + (size_t)i * LPE * FP + f] = pt[i * FP + f];
       }
     }
   }
@@ -584,6 +598,7 @@ void k_level2(KPtrs p, LevelArgs a) {
   const int e = lane / LPE, r = lane % LPE;
   const int ec = e < EPW ? e : EPW - 1;
   const int q = e < EPW ? r : 0;
+  select_run<R>(p, a.run0 + (int)blockIdx.y);
   const int g = blockIdx.x;
   const int elem = g * EPW + ec;
   const int cl = cluster_of(a, g * EPW);        // one cluster per workgroup (uniform)
@@ -606,7 +621,7 @@ void k_level2(KPtrs p, LevelArgs a) {
   R* const Qg = reinterpret_cast<R*>(p.Qe) + (size_t)g * B * NSLOT;
   R* const Qag = reinterpret_cast<R*>(p.Qa) + (size_t)g * JB * MM * 6 * NSLOT;
   const R* P = reinterpret_cast<const R*>(p.P) + (size_t)g * EPW * NPARAM + ec * NPARAM;
-  const int* FI = p.FI + (size_t)g * EPW * 8 + ec * 8;
+  const int* FI = p.FI + (size_t)g * EPW * FI_WORDS + ec * FI_WORDS;
   const size_t tg = (size_t)g * EPW * TS;        // this workgroup's first trace
 
   const bool is_stress = q < 6;
@@ -658,8 +673,9 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii) {
       const int i = 2 * w + ii;
-      const int nbr = FI[2 * i];
-      const int code = FI[2 * i + 1];
+      const int nbr = FI[3 * i];
+      const int code = FI[3 * i + 1];
+      const size_t aux = (size_t)FI[3 * i + 2];
       const int j = code & 15, rel = ((code >> 8) & 15) - 1;
       const R* own = T1 + (size_t)(n & 1) * Kp * tstride + tg + (ec * TS + (i * LPE + q) * FP);
       R* dmn = fac + ((i * 2 + 0) * LPE + q) * FS;
@@ -673,12 +689,12 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
           for (int f = 0; f < FP; ++f) dpl[f] = s[f];
         } else if (rel < 0) {
-          const R* s = T3 + (size_t)(n & 1) * Kp * tstride + nbo;
+          const R* s = T3 + ((size_t)(n & 1) * p.N3 + aux) * tstride + (size_t)(j * LPE + q) * FP;
 #pragma unroll
           for (int f = 0; f < FP; ++f) dpl[f] = s[f];
         } else {
           const int c = (n >> 1) & 1;
-          const R* s2 = T2 + (size_t)c * Kp * tstride + nbo;
+          const R* s2 = T2 + ((size_t)c * p.N2 + aux) * tstride + (size_t)(j * LPE + q) * FP;
           if ((n & 1) == 0) {
 #pragma unroll
             for (int f = 0; f < FP; ++f) dpl[f] = s2[f];
@@ -699,7 +715,7 @@ void k_level2(KPtrs p, LevelArgs a) {
       const int t = q + LPE * (w + 2 * rr);
       if (t < 4 * F) {
         const int i = t / F, f = t % F;
-        const int code = FI[2 * i + 1];
+        const int code = FI[3 * i + 1];
         const int bc = (code >> 4) & 15;
         const R* fp = P + 20 + 6 * i;
         R qm[9], qp[9], out[15];
@@ -793,9 +809,9 @@ void k_level2(KPtrs p, LevelArgs a) {
   // writes its own modes of the next derivative there and reads them back for
   // the time integrals, so no register copy of it is kept across the loop.
   const int nn = a.step_new[cl];
-  const int eflags = p.EF[elem];
+  const int eflags = FI[12];
   const bool need_b2 = __syncthreads_or((eflags & EF_HAS_FINER) != 0);
-  const int rec_slot = p.rec_slot ? p.rec_slot[elem] : -1;
+  const int rec_slot = FI[15];
   R te[NBX], t2[NBX];
   R dm[JW][MM][6];
 #pragma unroll
@@ -918,17 +934,17 @@ void k_level2(KPtrs p, LevelArgs a) {
         for (int f = 0; f < FP; ++f) T1[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
     }
     if ((eflags & EF_HAS_COARSER) && valid) {
-      R* T3 = reinterpret_cast<R*>(p.T3) + (size_t)((nn >> 1) & 1) * Kp * tstride + tg;
+      R* T3 = reinterpret_cast<R*>(p.T3) + ((size_t)((nn >> 1) & 1) * p.N3 + (size_t)FI[14]) * tstride;
       if ((nn & 1) == 0) {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T3[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) T3[q * FP + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
       } else {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T3[own + (2 * w + ii) * LPE * FP + f] += pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) T3[q * FP + (2 * w + ii) * LPE * FP + f] += pt[ii * FP + f];
       }
     }
     if (w == 0) RF::vol_grad_p0(full, G, gw0, gw1, gw2);
@@ -982,8 +998,8 @@ void k_level2(KPtrs p, LevelArgs a) {
     R pt[2 * FP];
     if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
     if (valid && (eflags & EF_HAS_FINER)) {
-      R* T2 = reinterpret_cast<R*>(p.T2) + (size_t)(nn & 1) * Kp * tstride + tg;
-      const int own = fresh(ec * TS + q * FP);
+      R* T2 = reinterpret_cast<R*>(p.T2) + ((size_t)(nn & 1) * p.N2 + (size_t)FI[13]) * tstride;
+      const int own = fresh(q * FP);
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
@@ -1043,7 +1059,7 @@ __global__ void k_sources(KPtrs p, LevelArgs a, SrcArgs s) {
                    stf_antiderivative(s.kind[src], s.par[2 * src], s.par[2 * src + 1], t0);
   const double inc = -s.moment[6 * src + qq] * s.phi[(size_t)src * B + b] * s.inv_det[src] * w;
   const int g = elem / EPW, e = elem % EPW;
-  R* Qe = reinterpret_cast<R*>(p.Qe);
+  R* Qe = reinterpret_cast<R*>(p.Qe) + (size_t)s.run[src] * p.run_qe;
   atomicAdd(&Qe[((size_t)g * B + b) * NSLOT + e * LPE + qq], R(inc));
 }
 
@@ -1052,9 +1068,12 @@ __global__ void k_sources(KPtrs p, LevelArgs a, SrcArgs s) {
 template <class R, int O, int M>
 __global__ void k_receivers(KPtrs p, LevelArgs a, RecArgs r) {
   constexpr int B = edg_gen::Ref<O>::B;
+  const int run = r.run0 + (int)blockIdx.y;
+  select_run<R>(p, run);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int rec = t / LPE, q = t % LPE;
   if (rec >= r.n) return;
+  double* const out = r.out + (size_t)run * r.n * r.ns * LPE;
   const int elem = r.elem[rec];
   if (elem >= a.end) return;
   const int cl = cluster_of(a, elem);
@@ -1080,25 +1099,26 @@ __global__ void k_receivers(KPtrs p, LevelArgs a, RecArgs r) {
       pw *= x;
       fact *= (double)(d + 1);
     }
-    r.out[((size_t)rec * r.ns + s) * LPE + q] = acc;
+    out[((size_t)rec * r.ns + s) * LPE + q] = acc;
   }
 }
 
 }  // namespace
 
 template <class R, int O, int M>
-int launch_level(const KPtrs& p, const LevelArgs& a, hipStream_t st) {
-  const int grid = (a.end + EPW - 1) / EPW;
-  if (grid <= 0) return 0;
+int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st) {
+  const int groups = (a.end + EPW - 1) / EPW;
+  if (groups <= 0 || runs <= 0) return 0;
+  const dim3 grid(groups, runs);
   if constexpr (std::is_same<R, float>::value && O >= 4) {
     if (a.kind == KIND_FUSED)
-      hipLaunchKernelGGL((k_level2<R, O, M, KIND_FUSED>), dim3(grid), dim3(128), 0, st, p, a);
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_FUSED>), grid, dim3(128), 0, st, p, a);
     else if (a.kind == KIND_PREDICT)
-      hipLaunchKernelGGL((k_level2<R, O, M, KIND_PREDICT>), dim3(grid), dim3(128), 0, st, p, a);
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_PREDICT>), grid, dim3(128), 0, st, p, a);
     else
-      hipLaunchKernelGGL((k_level2<R, O, M, KIND_NEIGHBOR>), dim3(grid), dim3(128), 0, st, p, a);
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_NEIGHBOR>), grid, dim3(128), 0, st, p, a);
   } else
-    hipLaunchKernelGGL((k_level<R, O, M>), dim3(grid), dim3(64), 0, st, p, a);
+    hipLaunchKernelGGL((k_level<R, O, M>), grid, dim3(64), 0, st, p, a);
   return (int)hipGetLastError();
 }
 
@@ -1112,17 +1132,17 @@ int launch_sources(const KPtrs& p, const LevelArgs& a, const SrcArgs& s, hipStre
 }
 
 template <class R, int O, int M>
-int launch_receivers(const KPtrs& p, const LevelArgs& a, const RecArgs& r, hipStream_t st) {
-  if (r.n <= 0) return 0;
+int launch_receivers(const KPtrs& p, const LevelArgs& a, const RecArgs& r, int runs, hipStream_t st) {
+  if (r.n <= 0 || runs <= 0) return 0;
   const int total = r.n * LPE;
-  hipLaunchKernelGGL((k_receivers<R, O, M>), dim3((total + 127) / 128), dim3(128), 0, st, p, a, r);
+  hipLaunchKernelGGL((k_receivers<R, O, M>), dim3((total + 127) / 128, runs), dim3(128), 0, st, p, a, r);
   return (int)hipGetLastError();
 }
 
 #define EDG_INST(R, O, M)                                                                        \
-  template int launch_level<R, O, M>(const KPtrs&, const LevelArgs&, hipStream_t);              \
+  template int launch_level<R, O, M>(const KPtrs&, const LevelArgs&, int, hipStream_t);         \
   template int launch_sources<R, O, M>(const KPtrs&, const LevelArgs&, const SrcArgs&, hipStream_t); \
-  template int launch_receivers<R, O, M>(const KPtrs&, const LevelArgs&, const RecArgs&, hipStream_t);
+  template int launch_receivers<R, O, M>(const KPtrs&, const LevelArgs&, const RecArgs&, int, hipStream_t);
 
 EDG_KERNEL_INSTANCES
 

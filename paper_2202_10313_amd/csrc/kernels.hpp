@@ -15,24 +15,36 @@ constexpr int KIND_PREDICT = 0;   // time kernel + volume + buffers (start of an
 constexpr int KIND_FUSED = 1;     // finish step n (surface) + predict step n+1
 constexpr int KIND_NEIGHBOR = 2;  // finish step n only (end of an advance)
 
+constexpr int MAX_RUNS = 32;       // independent runs sharing one mesh
+
 constexpr int EF_HAS_FINER = 1;    // some face neighbour is one cluster finer: export B2
 constexpr int EF_HAS_COARSER = 2;  // some face neighbour is one cluster coarser: export B3
 
+// Per-element integer record FI[Kp][FI_WORDS]:
+//   [3i+0] neighbour across face i (internal index, -1 = none)
+//   [3i+1] code = j | bc<<4 | (rel+1)<<8 (j: the neighbour's face, rel: its
+//          cluster minus ours)
+//   [3i+2] the neighbour's B2 slot (rel > 0) or B3 slot (rel < 0), else 0
+//   [12] EF_* flags, [13] own B2 slot, [14] own B3 slot (-1 = none),
+//   [15] receiver slot (-1 = none)
+constexpr int FI_WORDS = 16;
+
 struct KPtrs {
-  void* Qe;          // [G][B][63] elastic rows, slot 9e+q
-  void* Qa;          // [G][B][m][42] memory rows, slot 6e+q
-  const void* P;     // [Kp][NPARAM]
-  const int* FI;     // [Kp][4][2]: neighbour, code = j | bc<<4 | (rel+1)<<8
-  const int* EF;     // [Kp] EF_* flags
-  void* T1;          // [2][Kp][4][9][FP] B1 face traces
-  void* T2;          // [2][Kp][4][9][FP] B2 face traces
-  void* T3;          // [2][Kp][4][9][FP] B3 face traces
-  const int* rec_slot;  // [Kp] receiver-element slot or -1 (may be null)
-  void* recD;        // [slots][O][9][B] time derivatives of receiver elements
+  void* Qe;          // [run][G][B][63] elastic rows, slot 9e+q
+  void* Qa;          // [run][G][JB][m][6][63] memory variables of mode 9jb+q
+  const void* P;     // [Kp][NPARAM] (shared by all runs)
+  const int* FI;     // [Kp][FI_WORDS] (shared by all runs)
+  void* T1;          // [run][2][Kp][4][9][FP] B1 face traces (parity of the step)
+  void* T2;          // [run][2][N2][4][9][FP] B2 face traces of elements with a finer neighbour
+  void* T3;          // [run][2][N3][4][9][FP] B3 face traces of elements with a coarser neighbour
+  void* recD;        // [run][slots][O][9][B] time derivatives of receiver elements
   long long Kp;      // padded element count (multiple of 7)
+  long long N2, N3;  // B2 / B3 slots per parity
+  long long run_qe, run_qa, run_t1, run_t2, run_t3, run_recd;   // per-run strides (words)
 };
 
 struct LevelArgs {
+  int run0;          // runs run0 + blockIdx.y take part
   int end;           // internal slots [0, end) take part (clusters are contiguous, finest first)
   int kind;
   int n_clusters;
@@ -48,6 +60,7 @@ struct LevelArgs {
 
 struct SrcArgs {
   int n;
+  const int* run;         // [n] run of each source
   const int* elem;
   const int* kind;
   const double* par;      // [n][2]
@@ -63,15 +76,16 @@ struct RecArgs {
   const double* phi;      // [n][B]
   double dt_sample;
   long long ns;
-  double* out;            // [n][ns][9]
+  int run0;               // runs run0 + blockIdx.y take part
+  double* out;            // [run][n][ns][9]
 };
 
 template <class R, int O, int M>
-int launch_level(const KPtrs& p, const LevelArgs& a, hipStream_t st);
+int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st);
 template <class R, int O, int M>
 int launch_sources(const KPtrs& p, const LevelArgs& a, const SrcArgs& s, hipStream_t st);
 template <class R, int O, int M>
-int launch_receivers(const KPtrs& p, const LevelArgs& a, const RecArgs& r, hipStream_t st);
+int launch_receivers(const KPtrs& p, const LevelArgs& a, const RecArgs& r, int runs, hipStream_t st);
 
 // instantiated (precision, order, mechanisms) combinations
 #define EDG_FOR_EACH_VARIANT(X) \

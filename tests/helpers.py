@@ -57,9 +57,9 @@ def anelastic_setup(scale, order, n_clusters, seed=20, with_source=True, n_rec=6
     return dict(mesh=mesh, mat=mat, attn=attn, src=src, rec=rec)
 
 
-def gpu_context(w, order, n_clusters, fp64, lam=None, clusters=None, mechanisms=3):
+def gpu_context(w, order, n_clusters, fp64, lam=None, clusters=None, mechanisms=3, n_runs=1):
     from paper_2202_10313_amd import Context
-    ctx = Context(order, mechanisms=mechanisms, n_clusters=n_clusters, fp64=fp64, cfl=0.5, lam=lam)
+    ctx = Context(order, mechanisms=mechanisms, n_clusters=n_clusters, fp64=fp64, cfl=0.5, lam=lam, n_runs=n_runs)
     m = w["mesh"]
     ctx.upload_mesh(m["tet_verts"], m["tet_xyz"], m["face_bc"])
     a = w.get("attn")
