@@ -16,6 +16,12 @@ second is the value.  The roofline entry uses the per-launch durations of
 the element-update kernel from HIP events recorded on the library's stream
 during the same timed region.  The CPU baseline times the FP64 oracle on a
 bounded sample (a 6 x 6-column box of the same construction, three cycles).
+
+The "fused" entry runs 16 independent runs of the same workload in one
+context (one launch per LTS level for all runs), each with its own Ricker
+source (fc uniform in 1-3 Hz, random moment tensor, uniform location in the
+top 5 km), and reports run-element updates per second against the plain
+single-run value.
 """
 from __future__ import annotations
 
@@ -126,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fused-runs", type=int, default=16, help="runs of the fused batch line (<= 1: skip it)")
+    ap.add_argument("--fused-steps", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (profiler calibration of FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -154,37 +162,46 @@ def main():
     attn = synth.attenuation_inputs(mat, 3, 0.1, 10.0)
     src = synth.ricker_sources(22, 1, ((5000.0, 15000.0), (5000.0, 15000.0)), (1000.0, 5000.0), fc_range=(2.0, 2.0))
     rec = synth.surface_receivers(23, 64, ((1000.0, 19000.0), (1000.0, 19000.0)))
-
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    ctx = Context(args.order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream)
-    print("[bench] uploading", file=sys.stderr, flush=True)
-    ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
-    ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
-    ctx.upload_clusters(None)
-    info = ctx.get_clusters()
-    sync = info["sync_dt"]
-    ctx.set_sources(src["xyz"], src["moment"], STF_RICKER, src["stf_params"])
-    total_t = (args.warmup + args.steps) * sync
-    ctx.set_receivers(rec, 0.005, int(total_t / 0.005) + 2)
 
-    print(f"[bench] warmup {args.warmup} cycles", file=sys.stderr, flush=True)
-    ctx.advance_to(args.warmup * sync)
-    u0 = ctx.element_updates()
-    ctx.enable_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.advance_to((args.warmup + args.steps) * sync)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    updates = ctx.element_updates() - u0
-    ks = ctx.kernel_stats()
-    wall = t1 - t0
+    def measure(order, runs, steps, warmup):
+        """Advance `runs` runs of the workload (run r with its own Ricker
+        source) by warmup + steps LTS cycles; time the last `steps`."""
+        ctx = Context(order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream,
+                      n_runs=runs)
+        ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+        ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+        ctx.upload_clusters(None)
+        info = ctx.get_clusters()
+        sync = info["sync_dt"]
+        for r in range(runs):
+            s = src if runs == 1 else synth.ricker_sources(40 + r, 1, ((0.0, 20000.0), (0.0, 20000.0)), (0.0, 5000.0),
+                                                           fc_range=(1.0, 3.0))
+            ctx.set_sources(s["xyz"], s["moment"], STF_RICKER, s["stf_params"], run=r)
+        total_t = (warmup + steps) * sync
+        ctx.set_receivers(rec, 0.005, int(total_t / 0.005) + 2)
+        ctx.advance_to(warmup * sync)
+        u0 = ctx.element_updates()
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.advance_to((warmup + steps) * sync)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = dict(updates=ctx.element_updates() - u0, wall=t1 - t0, ks=ctx.kernel_stats(), info=info)
+        for r in range(runs):
+            if not np.all(np.isfinite(ctx.read_receivers(run=r))):
+                raise RuntimeError(f"non-finite seismograms in run {r}")
+        ctx.close()
+        return res
+
+    print(f"[bench] plain: 1 run, O={args.order}, warmup {args.warmup}, {args.steps} cycles", file=sys.stderr, flush=True)
+    m = measure(args.order, 1, args.steps, args.warmup)
+    info, ks, wall, updates = m["info"], m["ks"], m["wall"], m["updates"]
+    sync = info["sync_dt"]
     value = updates / wall
     print(f"[bench] timed {args.steps} cycles: {wall * 1e3:.1f} ms, {updates} element updates", file=sys.stderr, flush=True)
-    seis = ctx.read_receivers()
-    if not np.all(np.isfinite(seis)):
-        raise RuntimeError("non-finite seismograms")
 
     cl = info["clusters"].astype(np.int64)
     nbr = face_neighbours(mesh["tet_verts"])
@@ -208,7 +225,7 @@ def main():
         "frac": max(frac_hbm, frac_alu),
         "traffic": traffic,
         "traffic_unit": "bytes/launch",
-        "kernel": f"k_level2<float,{args.order},3>" if args.order >= 4 else f"k_level<float,{args.order},3>",
+        "kernel": f"k_level2<float,{args.order},3,FUSED>" if args.order >= 4 else f"k_level<float,{args.order},3>",
         "launches": ks["launches"],
         "avg_launch_ms": per_launch_ms,
         "element_updates_per_launch": upd_per_launch,
@@ -217,6 +234,17 @@ def main():
         "alu": {"achieved_TFLOPs": achieved_tf, "peak_TFLOPs": VALU_FP32_PEAK_TFLOPS, "frac": frac_alu,
                 "flops_per_update": PAPER_FLOPS_ALL_SPARSITY},
     }
+    fused = None
+    if args.fused_runs > 1:
+        print(f"[bench] fused: {args.fused_runs} runs, O={args.order}, warmup 1, {args.fused_steps} cycles",
+              file=sys.stderr, flush=True)
+        f = measure(args.order, args.fused_runs, args.fused_steps, 1)
+        fv = f["updates"] / f["wall"]
+        fused = {"runs": args.fused_runs, "value": fv, "unit": "run-elem-updates/s", "ratio_vs_plain": fv / value,
+                 "steps": args.fused_steps, "ms_per_step": f["wall"] * 1e3 / args.fused_steps,
+                 "avg_launch_ms": f["ks"]["total_ms"] / max(f["ks"]["launches"], 1),
+                 "sources": "one Ricker per run: fc U[1,3] Hz, random moment tensor, uniform in the top 5 km"}
+        print(f"[bench] fused: {fv:.4g} run-element updates/s ({fv / value:.2f}x plain)", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": value,
@@ -237,10 +265,12 @@ def main():
             "lambda": info["lam"], "cluster_sizes": counts.tolist(),
             "theoretical_lts_speedup": info["speedup"],
             "gts_equivalent_rate": K * (args.steps * sync / info["dt_min"]) / wall,
-            "plain_only": "fused (16-run) and fwd+adjoint forms are not built",
+            "adjoint": "not built",
         },
         "roofline": roofline,
     }
+    if fused is not None:
+        out["fused"] = fused
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
