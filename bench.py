@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fused-runs", type=int, default=16, help="runs of the fused batch line (<= 1: skip it)")
     ap.add_argument("--fused-steps", type=int, default=4)
+    ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch every level eagerly")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false", help="keep the default launch plan")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (profiler calibration of FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -142,7 +144,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2202_10313_amd import Context, STF_RICKER
+    from paper_2202_10313_amd import FLAG_GRAPH, Context, STF_RICKER
 
     if args.copy_calibration:
         n = 1 << 29                                   # 2 GiB of float32
@@ -167,9 +169,11 @@ def main():
 
     def measure(order, runs, steps, warmup):
         """Advance `runs` runs of the workload (run r with its own Ricker
-        source) by warmup + steps LTS cycles; time the last `steps`."""
+        source): the autotuner's cycles (one per candidate launch plan), then
+        warmup + steps LTS cycles, timing the last `steps` (full cycles
+        replayed as captured HIP graphs)."""
         ctx = Context(order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream,
-                      n_runs=runs)
+                      n_runs=runs, flags=FLAG_GRAPH if args.graph else 0)
         ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
         ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
         ctx.upload_clusters(None)
@@ -179,17 +183,20 @@ def main():
             s = src if runs == 1 else synth.ricker_sources(40 + r, 1, ((0.0, 20000.0), (0.0, 20000.0)), (0.0, 5000.0),
                                                            fc_range=(1.0, 3.0))
             ctx.set_sources(s["xyz"], s["moment"], STF_RICKER, s["stf_params"], run=r)
-        total_t = (warmup + steps) * sync
+        total_t = (warmup + steps + 16) * sync
         ctx.set_receivers(rec, 0.005, int(total_t / 0.005) + 2)
-        ctx.advance_to(warmup * sync)
+        plan, tuned_ms = ctx.autotune(cycles=1) if args.autotune else (ctx.get_plan(), None)
+        print(f"[bench] launch plan {plan} ({tuned_ms} ms per cycle while tuning)", file=sys.stderr, flush=True)
+        t_start = ctx.time()
+        ctx.advance_to(t_start + warmup * sync)
         u0 = ctx.element_updates()
         ctx.enable_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.advance_to((warmup + steps) * sync)
+        ctx.advance_to(t_start + (warmup + steps) * sync)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        res = dict(updates=ctx.element_updates() - u0, wall=t1 - t0, ks=ctx.kernel_stats(), info=info)
+        res = dict(updates=ctx.element_updates() - u0, wall=t1 - t0, ks=ctx.kernel_stats(), info=info, plan=plan)
         for r in range(runs):
             if not np.all(np.isfinite(ctx.read_receivers(run=r))):
                 raise RuntimeError(f"non-finite seismograms in run {r}")
@@ -227,6 +234,8 @@ def main():
         "traffic_unit": "bytes/launch",
         "kernel": f"k_level2<float,{args.order},3,FUSED>" if args.order >= 4 else f"k_level<float,{args.order},3>",
         "launches": ks["launches"],
+        "launch_plan": m["plan"],
+        "graph": bool(args.graph),
         "avg_launch_ms": per_launch_ms,
         "element_updates_per_launch": upd_per_launch,
         "algorithmic_bytes_per_update": bpu,
@@ -243,6 +252,7 @@ def main():
         fused = {"runs": args.fused_runs, "value": fv, "unit": "run-elem-updates/s", "ratio_vs_plain": fv / value,
                  "steps": args.fused_steps, "ms_per_step": f["wall"] * 1e3 / args.fused_steps,
                  "avg_launch_ms": f["ks"]["total_ms"] / max(f["ks"]["launches"], 1),
+                 "launch_plan": f["plan"],
                  "sources": "one Ricker per run: fc U[1,3] Hz, random moment tensor, uniform in the top 5 km"}
         print(f"[bench] fused: {fv:.4g} run-element updates/s ({fv / value:.2f}x plain)", file=sys.stderr, flush=True)
     out = {

@@ -72,8 +72,20 @@ typedef struct {
   double lambda;       /* lambda in (0.5, 1]; <= 0 searches 0.51..1.00 (max speedup, ties -> larger) */
   void* hip_stream;    /* hipStream_t the library launches on (NULL: its own stream) */
   int32_t device;      /* HIP device ordinal */
-  uint32_t flags;      /* reserved, 0 */
+  uint32_t flags;      /* EDG_FLAG_* */
 } edg_config;
+
+#define EDG_FLAG_GRAPH 1u  /* replay every full LTS cycle but the last of an edg_advance_to call as one
+                              captured HIP graph (kernel nodes only; recaptured after a change of
+                              sources, receivers, clusters or launch plan) */
+
+/* Launch plan of the element-update kernel.  Every plan gives bit-identical
+ * results; only the speed differs. */
+typedef struct {
+  int32_t xcd_remap;  /* 1: the workgroups dealt to one XCD take a contiguous range of element
+                         groups (neighbour traces then stay in that XCD's L2) */
+  int32_t run_chunk;  /* runs per launch (0 = all runs in one launch) */
+} edg_plan;
 
 /* Create a context on cfg->device.  *out receives the handle (NULL on
  * failure; creation errors are returned only as codes). */
@@ -164,6 +176,19 @@ int edg_kernel_stats(const edg_ctx* ctx, int64_t* launches, double* total_ms, in
 
 /* Element updates (element x own step x run) performed so far. */
 int64_t edg_element_updates(const edg_ctx* ctx);
+
+/* Set / get the launch plan (default {0, 0}).  EDG_EINVAL for values out of
+ * range. */
+int edg_set_plan(edg_ctx* ctx, const edg_plan* plan);
+int edg_get_plan(const edg_ctx* ctx, edg_plan* plan);
+
+/* Autotuner: advances the simulation by `cycles` LTS cycles per candidate plan
+ * (XCD remap on/off x runs per launch: all, 16, 8, 4), timing the element
+ * kernel of each, and keeps the fastest.  The simulated time moves on by
+ * (number of candidates) x cycles x sync_dt; the results are the same as with
+ * any other plan.  best / ms_per_cycle (kernel time of the best candidate)
+ * may be NULL.  The tuning cycles are left out of edg_kernel_stats. */
+int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cycle);
 
 /* Destroy the context and free its device memory (NULL is ignored). */
 void edg_destroy(edg_ctx* ctx);

@@ -19,19 +19,27 @@ ERRORS = {-1: "EDG_EINVAL", -2: "EDG_ESTATE", -3: "EDG_ENOMEM", -4: "EDG_EHIP",
           -5: "EDG_ENOTSYNC", -6: "EDG_EMESH", -7: "EDG_ECAP"}
 BC_INTERIOR, BC_FREE, BC_ABSORB = 0, 1, 2
 STF_RICKER, STF_HANN = 0, 1
+FLAG_GRAPH = 1
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = ["edg_create", "edg_upload_mesh", "edg_upload_materials", "edg_upload_clusters",
            "edg_get_clusters", "edg_set_initial", "edg_set_sources", "edg_set_receivers",
            "edg_advance_to", "edg_read_receivers", "edg_read_dofs", "edg_time", "edg_last_error",
-           "edg_enable_timing", "edg_kernel_stats", "edg_element_updates", "edg_destroy",
-           "edg_reference_matrices", "edg_cluster_host"]
+           "edg_enable_timing", "edg_kernel_stats", "edg_element_updates", "edg_set_plan", "edg_get_plan",
+           "edg_autotune", "edg_destroy", "edg_reference_matrices", "edg_cluster_host"]
 
 
 class EdgError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
         self.code = code
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("xcd_remap", ctypes.c_int32), ("run_chunk", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(xcd_remap=self.xcd_remap, run_chunk=self.run_chunk)
 
 
 class Config(ctypes.Structure):
@@ -72,6 +80,9 @@ def lib():
             "edg_enable_timing": (ctypes.c_int, [_P, _I32]),
             "edg_kernel_stats": (ctypes.c_int, [_P, _P, _P, _P]),
             "edg_element_updates": (ctypes.c_int64, [_P]),
+            "edg_set_plan": (ctypes.c_int, [_P, _P]),
+            "edg_get_plan": (ctypes.c_int, [_P, _P]),
+            "edg_autotune": (ctypes.c_int, [_P, _I32, _P, _P]),
             "edg_destroy": (None, [_P]),
             "edg_reference_matrices": (ctypes.c_int, [_I32, _P, _P]),
             "edg_cluster_host": (ctypes.c_int, [_I64, _P, _P, _I32, ctypes.c_double, _P, _P, _P]),
@@ -110,10 +121,10 @@ class Context:
     and receivers of one device stream."""
 
     def __init__(self, order, mechanisms=0, n_clusters=1, fp64=False, cfl=0.5, lam=1.0,
-                 stream=None, device=0, n_runs=1):
+                 stream=None, device=0, n_runs=1, flags=0):
         self._L = lib()
         cfg = Config(order, mechanisms, n_runs, n_clusters, int(bool(fp64)), float(cfl),
-                     -1.0 if lam is None else float(lam), stream, device, 0)
+                     -1.0 if lam is None else float(lam), stream, device, int(flags))
         h = _P()
         rc = self._L.edg_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != EDG_OK:
@@ -204,6 +215,23 @@ class Context:
 
     def element_updates(self):
         return self._L.edg_element_updates(self.h)
+
+    def set_plan(self, xcd_remap=0, run_chunk=0):
+        pl = Plan(int(xcd_remap), int(run_chunk))
+        self._chk(self._L.edg_set_plan(self.h, ctypes.byref(pl)))
+
+    def get_plan(self):
+        pl = Plan()
+        self._chk(self._L.edg_get_plan(self.h, ctypes.byref(pl)))
+        return pl.as_dict()
+
+    def autotune(self, cycles=1):
+        """Advance `cycles` LTS cycles per candidate plan and keep the fastest;
+        returns (plan, kernel ms per cycle of that plan)."""
+        pl = Plan()
+        ms = ctypes.c_double()
+        self._chk(self._L.edg_autotune(self.h, int(cycles), ctypes.byref(pl), ctypes.byref(ms)))
+        return pl.as_dict(), ms.value
 
 
 def reference_matrices(order):

@@ -86,10 +86,17 @@ struct edg_ctx {
 
   std::vector<std::vector<double>> perm_mats;  // 24 B x B conversion matrices
 
+  // launch plan (all plans give bit-identical results) and cycle graph
+  edg_plan plan{0, 0};
+  DevBuf dclock;                     // level at the start of the current cycle (device)
+  hipGraphExec_t cycle_exec = nullptr;
+  hipGraph_t cycle_graph = nullptr;
+
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
   std::vector<int64_t> ev_updates;
+  std::vector<int> ev_launches;
   int64_t t_launches = 0, t_updates = 0;
   double t_ms = 0;
 
@@ -496,40 +503,69 @@ LevelArgs base_args(const edg_ctx* c) {
     }
   }
   for (int l = 0; l < c->M; ++l) a.omega[l] = c->omega[l];
+  a.clock = (const long long*)c->dclock.p;
+  a.xcd_remap = c->plan.xcd_remap;
   return a;
 }
 
-int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, int64_t upd) {
-  if (c->timing) {
-    if (c->ev_used == c->ev_pool.size()) {
-      hipEvent_t e0, e1;
-      HIPCHK(c, hipEventCreate(&e0));
-      HIPCHK(c, hipEventCreate(&e1));
-      c->ev_pool.push_back({e0, e1});
-    }
-    auto& ev = c->ev_pool[c->ev_used++];
-    c->ev_updates.push_back(upd);
-    HIPCHK(c, hipEventRecord(ev.first, c->stream));
-    int rc = fn.level(p, a, c->runs, c->stream);
+// one LTS level for all runs, in chunks of plan.run_chunk runs per launch
+int launch_runs(edg_ctx* c, const Fns& fn, const KPtrs& p, LevelArgs a) {
+  const int chunk = c->plan.run_chunk > 0 ? std::min(c->plan.run_chunk, c->runs) : c->runs;
+  for (int r0 = 0; r0 < c->runs; r0 += chunk) {
+    a.run0 = r0;
+    const int rc = fn.level(p, a, std::min(chunk, c->runs - r0), c->stream);
     if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
-    HIPCHK(c, hipEventRecord(ev.second, c->stream));
-    return 0;
   }
-  int rc = fn.level(p, a, c->runs, c->stream);
-  if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return 0;
+}
+
+int timed_begin(edg_ctx* c, int64_t upd, int launches) {
+  if (!c->timing) return 0;
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    c->ev_pool.push_back({e0, e1});
+  }
+  c->ev_updates.push_back(upd);
+  c->ev_launches.push_back(launches);
+  HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used].first, c->stream));
+  return 0;
+}
+
+int timed_end(edg_ctx* c) {
+  if (!c->timing) return 0;
+  HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used++].second, c->stream));
+  return 0;
+}
+
+// the captured cycle refers to argument values of the moment: drop it when they change
+void drop_graph(edg_ctx* c) {
+  if (c->cycle_exec) (void)hipGraphExecDestroy(c->cycle_exec);
+  if (c->cycle_graph) (void)hipGraphDestroy(c->cycle_graph);
+  c->cycle_exec = nullptr;
+  c->cycle_graph = nullptr;
+}
+
+int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, int64_t upd) {
+  int rc;
+  if ((rc = timed_begin(c, upd, 1))) return rc;
+  if ((rc = launch_runs(c, fn, p, a))) return rc;
+  return timed_end(c);
 }
 
 }  // namespace
 
 edg_ctx::~edg_ctx() {
   for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
-                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out})
+                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock})
     dev_free(*b);
   for (auto& e : ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  if (cycle_exec) (void)hipGraphExecDestroy(cycle_exec);
+  if (cycle_graph) (void)hipGraphDestroy(cycle_graph);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -789,6 +825,9 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   c->n_rec = 0;
   c->n_src = 0;
   for (auto& v : c->src_of_run) v.clear();
+  drop_graph(c);
+  if ((rc = dev_alloc(c, c->dclock, sizeof(long long)))) return rc;
+  HIPCHK(c, hipMemset(c->dclock.p, 0, sizeof(long long)));
   c->level = 0;
   for (int l = 0; l < MAX_CLUSTERS; ++l) c->nstep[l] = 0;
   c->updates = 0;
@@ -849,6 +888,7 @@ int edg_set_sources(edg_ctx* c, int32_t run, int64_t n, const double* xyz, const
     list.push_back(std::move(src));
   }
   c->src_of_run[run] = std::move(list);
+  drop_graph(c);
   // the device list holds the sources of every run
   std::vector<int> rn, el, kd;
   std::vector<double> pr, mo, phi, idet;
@@ -906,11 +946,115 @@ int edg_set_receivers(edg_ctx* c, int64_t n, const double* xyz, double dt_sample
   if ((rc = dev_alloc(c, c->r_out, (size_t)c->runs * std::max<int64_t>(n, 1) * ns * LPE * sizeof(double))))
     return rc;
   HIPCHK(c, hipMemset(c->r_out.p, 0, c->r_out.bytes));
+  drop_graph(c);
   c->n_rec = (int)n;
   c->rec_ns = ns;
   c->rec_dt = dt_sample;
   return EDG_OK;
 }
+
+namespace {
+
+struct AdvanceArgs {
+  Fns fn;
+  KPtrs p;
+  SrcArgs sa;
+  RecArgs ra;
+};
+
+AdvanceArgs advance_args(edg_ctx* c) {
+  AdvanceArgs A;
+  A.fn = pick(c->cfg.fp64, c->O, c->M);
+  A.p = kptrs(c);
+  A.sa.n = c->n_src;
+  A.sa.run = (const int*)c->s_run.p;
+  A.sa.elem = (const int*)c->s_elem.p;
+  A.sa.kind = (const int*)c->s_kind.p;
+  A.sa.par = (const double*)c->s_par.p;
+  A.sa.moment = (const double*)c->s_mom.p;
+  A.sa.phi = (const double*)c->s_phi.p;
+  A.sa.inv_det = (const double*)c->s_idet.p;
+  A.ra.n = c->n_rec;
+  A.ra.elem = (const int*)c->r_elem.p;
+  A.ra.slot = (const int*)c->r_slot.p;
+  A.ra.phi = (const double*)c->r_phi.p;
+  A.ra.dt_sample = c->rec_dt;
+  A.ra.ns = c->rec_ns;
+  A.ra.run0 = 0;
+  A.ra.out = (double*)c->r_out.p;
+  return A;
+}
+
+// finest level j (1..2^(Nc-1)) of a cycle: the coarsest cluster that ends a step there
+int level_lmax(const edg_ctx* c, int64_t j) {
+  int lmax = 0;
+  for (int l = 1; l < c->cfg.n_clusters; ++l)
+    if (j % ((int64_t)1 << l) == 0) lmax = l;
+  return lmax;
+}
+
+int64_t level_updates(const edg_ctx* c, int lmax) {
+  int64_t u = 0;
+  for (int l = 0; l <= lmax; ++l) u += c->cl_count[l] * c->runs;
+  return u;
+}
+
+// The launches of one LTS cycle (Sec. V-B: per finest level, the sources of
+// the steps that end there, the fused finish-and-predict launch, the
+// receivers of the new predictions), then the device clock tick.  `last`:
+// the final level only finishes (no prediction is needed after the advance).
+// `timed`: per-level events (not inside a graph capture).
+int emit_cycle(edg_ctx* c, const AdvanceArgs& A, bool last, bool timed) {
+  const int64_t per = (int64_t)1 << (c->cfg.n_clusters - 1);
+  int rc;
+  for (int64_t j = 1; j <= per; ++j) {
+    const int lmax = level_lmax(c, j);
+    LevelArgs a = base_args(c);
+    a.jrel = (int)j;
+    a.end = c->cl_end[lmax];
+    if (c->n_src > 0 && (rc = A.fn.src(A.p, a, A.sa, c->stream)))
+      return fail(c, EDG_EHIP, std::string("source kernel: ") + hipGetErrorString((hipError_t)rc));
+    const bool fin = last && j == per;
+    a.kind = fin ? KIND_NEIGHBOR : KIND_FUSED;
+    if (timed) {
+      if ((rc = launch_timed(c, A.fn, A.p, a, level_updates(c, lmax)))) return rc;
+    } else if ((rc = launch_runs(c, A.fn, A.p, a))) {
+      return rc;
+    }
+    if (!fin && c->n_rec > 0 && (rc = A.fn.rec(A.p, a, A.ra, c->runs, c->stream)))
+      return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
+  }
+  if ((rc = launch_tick((long long*)c->dclock.p, per, c->stream)))
+    return fail(c, EDG_EHIP, std::string("clock kernel: ") + hipGetErrorString((hipError_t)rc));
+  return 0;
+}
+
+int64_t cycle_updates(const edg_ctx* c) {
+  const int64_t per = (int64_t)1 << (c->cfg.n_clusters - 1);
+  int64_t u = 0;
+  for (int64_t j = 1; j <= per; ++j) u += level_updates(c, level_lmax(c, j));
+  return u;
+}
+
+// capture one full (non-final) cycle as a graph: only kernel launches, no
+// memory set or copy nodes
+int capture_cycle(edg_ctx* c, const AdvanceArgs& A) {
+  drop_graph(c);
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  const int rc = emit_cycle(c, A, false, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(c, EDG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  c->cycle_graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->cycle_exec, g, nullptr, nullptr, 0));
+  return 0;
+}
+
+}  // namespace
 
 int edg_advance_to(edg_ctx* c, double t) {
   if (!c) return EDG_EINVAL;
@@ -920,76 +1064,103 @@ int edg_advance_to(edg_ctx* c, double t) {
   const double sync = c->dt_cl[Nc - 1];
   const double t_now = (double)c->level * c->dt_cl[0];
   const double cycles = (t - t_now) / sync;
-  const double nc = std::nearbyint(cycles);
-  if (nc < 0 || std::fabs(cycles - nc) > 1e-9 * std::max(1.0, std::fabs(cycles)))
+  const double ncd = std::nearbyint(cycles);
+  if (ncd < 0 || std::fabs(cycles - ncd) > 1e-9 * std::max(1.0, std::fabs(cycles)))
     return fail(c, EDG_ENOTSYNC, "time is not a synchronisation point after the current time");
-  if (nc == 0) return EDG_OK;
+  if (ncd == 0) return EDG_OK;
+  const int64_t nc = (int64_t)ncd;
   const int64_t per = (int64_t)1 << (Nc - 1);
-  const int64_t L = (int64_t)nc * per;
-  const Fns fn = pick(c->cfg.fp64, c->O, c->M);
-  const KPtrs p = kptrs(c);
-  SrcArgs sa;
-  sa.n = c->n_src;
-  sa.run = (const int*)c->s_run.p;
-  sa.elem = (const int*)c->s_elem.p;
-  sa.kind = (const int*)c->s_kind.p;
-  sa.par = (const double*)c->s_par.p;
-  sa.moment = (const double*)c->s_mom.p;
-  sa.phi = (const double*)c->s_phi.p;
-  sa.inv_det = (const double*)c->s_idet.p;
-  RecArgs ra;
-  ra.n = c->n_rec;
-  ra.elem = (const int*)c->r_elem.p;
-  ra.slot = (const int*)c->r_slot.p;
-  ra.phi = (const double*)c->r_phi.p;
-  ra.dt_sample = c->rec_dt;
-  ra.ns = c->rec_ns;
-  ra.run0 = 0;
-  ra.out = (double*)c->r_out.p;
+  const AdvanceArgs A = advance_args(c);
+  const bool graph = (c->cfg.flags & EDG_FLAG_GRAPH) != 0;
   c->ev_used = 0;
   c->ev_updates.clear();
+  c->ev_launches.clear();
 
+  // predict every element at the start (level offset 0)
   LevelArgs a = base_args(c);
   a.kind = KIND_PREDICT;
+  a.jrel = 0;
   a.end = c->cl_end[Nc - 1];
-  for (int l = 0; l < Nc; ++l) a.step_new[l] = (int)c->nstep[l];
-  int rc = launch_timed(c, fn, p, a, 0);
+  int rc = launch_timed(c, A.fn, A.p, a, 0);
   if (rc) return rc;
-  if (c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->runs, c->stream)))
+  if (c->n_rec > 0 && (rc = A.fn.rec(A.p, a, A.ra, c->runs, c->stream)))
     return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
-  for (int64_t j = 1; j <= L; ++j) {
-    const int64_t g = c->level + j;
-    int lmax = 0;
-    for (int l = 1; l < Nc; ++l)
-      if (g % ((int64_t)1 << l) == 0) lmax = l;
-    a = base_args(c);
-    a.end = c->cl_end[lmax];
-    int64_t upd = 0;
-    for (int l = 0; l <= lmax; ++l) upd += c->cl_count[l] * c->runs;
-    for (int l = 0; l <= lmax; ++l) {
-      a.step_fin[l] = (int)c->nstep[l];
-      a.step_new[l] = (int)c->nstep[l] + 1;
+  for (int64_t k = 0; k < nc; ++k) {
+    const bool last = k + 1 == nc;
+    if (graph && !last) {
+      if (!c->cycle_exec && (rc = capture_cycle(c, A))) return rc;
+      if ((rc = timed_begin(c, cycle_updates(c), (int)per))) return rc;
+      HIPCHK(c, hipGraphLaunch(c->cycle_exec, c->stream));
+      if ((rc = timed_end(c))) return rc;
+    } else if ((rc = emit_cycle(c, A, last, true))) {
+      return rc;
     }
-    if (c->n_src > 0 && (rc = fn.src(p, a, sa, c->stream)))
-      return fail(c, EDG_EHIP, std::string("source kernel: ") + hipGetErrorString((hipError_t)rc));
-    a.kind = j < L ? KIND_FUSED : KIND_NEIGHBOR;
-    if ((rc = launch_timed(c, fn, p, a, upd))) return rc;
-    for (int l = 0; l <= lmax; ++l) c->nstep[l]++;
-    c->updates += upd;
-    if (j < L && c->n_rec > 0 && (rc = fn.rec(p, a, ra, c->runs, c->stream)))
-      return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
+    c->updates += cycle_updates(c);
   }
-  c->level += L;
+  c->level += nc * per;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->timing) {
     for (size_t i = 0; i < c->ev_used; ++i) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[i].first, c->ev_pool[i].second));
       c->t_ms += ms;
-      c->t_launches++;
+      c->t_launches += c->ev_launches[i];
       c->t_updates += c->ev_updates[i];
     }
   }
+  return EDG_OK;
+}
+
+int edg_set_plan(edg_ctx* c, const edg_plan* plan) {
+  if (!c) return EDG_EINVAL;
+  if (!plan || (plan->xcd_remap != 0 && plan->xcd_remap != 1) || plan->run_chunk < 0 || plan->run_chunk > MAX_RUNS)
+    return fail(c, EDG_EINVAL, "bad launch plan");
+  c->plan = *plan;
+  drop_graph(c);
+  return EDG_OK;
+}
+
+int edg_get_plan(const edg_ctx* c, edg_plan* plan) {
+  if (!c || !plan) return EDG_EINVAL;
+  *plan = c->plan;
+  return EDG_OK;
+}
+
+int edg_autotune(edg_ctx* c, int32_t cycles, edg_plan* best_out, double* best_ms) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (cycles < 1) return fail(c, EDG_EINVAL, "cycles must be positive");
+  std::vector<edg_plan> cand;
+  for (int xcd = 0; xcd <= 1; ++xcd)
+    for (int chunk : {0, 16, 8, 4})
+      if (chunk == 0 || chunk < c->runs) cand.push_back(edg_plan{xcd, chunk});
+  const bool timing = c->timing;
+  const int64_t l0 = c->t_launches, u0 = c->t_updates;
+  const double m0 = c->t_ms;
+  const double sync = c->dt_cl[c->cfg.n_clusters - 1];
+  edg_plan best = c->plan;
+  double best_t = 1e300;
+  int rc;
+  for (const edg_plan& pl : cand) {
+    if ((rc = edg_set_plan(c, &pl))) return rc;
+    c->timing = true;
+    const double before = c->t_ms;
+    rc = edg_advance_to(c, edg_time(c) + cycles * sync);
+    const double spent = c->t_ms - before;
+    c->timing = timing;
+    if (rc) return rc;
+    if (spent < best_t) {
+      best_t = spent;
+      best = pl;
+    }
+  }
+  // the tuning cycles do not count in the kernel statistics
+  c->t_launches = l0;
+  c->t_updates = u0;
+  c->t_ms = m0;
+  if ((rc = edg_set_plan(c, &best))) return rc;
+  if (best_out) *best_out = best;
+  if (best_ms) *best_ms = best_t / cycles;
   return EDG_OK;
 }
 

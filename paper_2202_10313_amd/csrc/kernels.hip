@@ -140,6 +140,29 @@ __device__ __forceinline__ void godunov(const R* qm, const R* qp, R nx, R ny, R 
   out[14] = hs * (nx * vz + nz * vx);
 }
 
+// Steps of cluster cl at the processed level (see LevelArgs::clock).
+__device__ __forceinline__ int step_new_of(const LevelArgs& a, int cl) {
+  return (int)((*a.clock + a.jrel) >> cl);
+}
+__device__ __forceinline__ int step_fin_of(const LevelArgs& a, int cl) { return step_new_of(a, cl) - 1; }
+
+// Linear workgroup id -> (element group, run).  Workgroups are dealt to the
+// 8 XCDs round robin; with xcd_remap the ids of one XCD cover a contiguous
+// range of the (run-major) group space, so neighbouring elements share that
+// XCD's L2.  A bijection for any grid size.
+__device__ __forceinline__ void group_and_run(const LevelArgs& a, int& g, int& run) {
+  const int nx = gridDim.x;
+  int lin = blockIdx.x + blockIdx.y * nx;
+  if (a.xcd_remap) {
+    const int total = nx * gridDim.y;
+    const int q = total / 8, r = total % 8;
+    const int x = lin % 8, k = lin / 8;
+    lin = x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+  }
+  g = lin % nx;
+  run = a.run0 + lin / nx;
+}
+
 // State arrays are stacked run after run: the pointers of one run.
 template <class R>
 __device__ __forceinline__ void select_run(KPtrs& p, int run) {
@@ -165,8 +188,9 @@ void k_level(KPtrs p, LevelArgs a) {
   const int e = lane / LPE, r = lane % LPE;
   const int ec = e < EPW ? e : EPW - 1;     // lane 63 duplicates lane 54 (same element, same row)
   const int q = e < EPW ? r : 0;
-  select_run<R>(p, a.run0 + (int)blockIdx.y);
-  const int g = blockIdx.x;
+  int g, run;
+  group_and_run(a, g, run);
+  select_run<R>(p, run);
   const int elem = g * EPW + ec;
   const int cl = cluster_of(a, g * EPW);        // one cluster per workgroup (uniform)
   const bool valid = (e < EPW) && (elem < a.cl_vend[cl]);
@@ -227,7 +251,7 @@ void k_level(KPtrs p, LevelArgs a) {
   // through the LDS area `coup`)
   bool coup_pending = false;
   if (a.kind != KIND_PREDICT) {
-    const int n = a.step_fin[cl];
+    const int n = step_fin_of(a, cl);
     const R* T1 = reinterpret_cast<const R*>(p.T1);
     const R* T2 = reinterpret_cast<const R*>(p.T2);
     const R* T3 = reinterpret_cast<const R*>(p.T3);
@@ -354,7 +378,7 @@ void k_level(KPtrs p, LevelArgs a) {
   }
 
   // ------------------------------------------------ time kernel: predict step nn
-  const int nn = a.step_new[cl];
+  const int nn = step_new_of(a, cl);
   const int eflags = FI[12];
   const bool need_b2 = __any((eflags & EF_HAS_FINER) != 0);
   const int rec_slot = FI[15];
@@ -577,11 +601,8 @@ __device__ __forceinline__ int gslot(int row, int dir) {
 // KIND is the launch kind (KIND_PREDICT, KIND_FUSED, KIND_NEIGHBOR) as a
 // template parameter: one code path per kernel keeps the register allocation
 // of the fused path free of the neighbour-only exit.
-#ifndef EDG_LEVEL2_WAVES
-#define EDG_LEVEL2_WAVES 2
-#endif
 template <class R, int O, int M, int KIND>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(EDG_LEVEL2_WAVES, 4)))
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 4)))
 void k_level2(KPtrs p, LevelArgs a) {
   using RF = edg_gen::Ref<O>;
   using L = Lds2<R, O, M>;
@@ -598,8 +619,9 @@ void k_level2(KPtrs p, LevelArgs a) {
   const int e = lane / LPE, r = lane % LPE;
   const int ec = e < EPW ? e : EPW - 1;
   const int q = e < EPW ? r : 0;
-  select_run<R>(p, a.run0 + (int)blockIdx.y);
-  const int g = blockIdx.x;
+  int g, run;
+  group_and_run(a, g, run);
+  select_run<R>(p, run);
   const int elem = g * EPW + ec;
   const int cl = cluster_of(a, g * EPW);        // one cluster per workgroup (uniform)
   const bool valid = (e < EPW) && (elem < a.cl_vend[cl]);
@@ -648,15 +670,23 @@ void k_level2(KPtrs p, LevelArgs a) {
   R* const gw0 = grad + gslot(q, 0) * BS;
   R* const gw1 = grad + gslot(q, 1) * BS;
   R* const gw2 = grad + gslot(q, 2) * BS;
-  int rA = 0, rB = 0, rC = 0;
-  if (!is_stress) {
+  // Star products without divergence: every lane forms
+  //   wabc (g[sa] + g[sb] + g[sc]) + wde (g[sd] + g[se]) + wc coupling
+  // stress row ij: lambda delta_ij div v + mu (d_j v_i + d_i v_j) + coupling,
+  // velocity row i: (1/rho) sum_d d_d sigma_id (the last two reads unused).
+  int sa, sb, sc, sd, se;
+  R wabc, wde, wc;
+  if (is_stress) {
+    sa = gslot(6, 0) * BS; sb = gslot(7, 1) * BS; sc = gslot(8, 2) * BS;
+    sd = gslot(6 + qi, qj) * BS; se = gslot(6 + qj, qi) * BS;
+    wabc = lam * delta; wde = mu; wc = R(1);
+  } else {
     const int i = q - 6;
-    rA = gslot(sym_index(i, 0), 0) * BS;
-    rB = gslot(sym_index(i, 1), 1) * BS;
-    rC = gslot(sym_index(i, 2), 2) * BS;
+    sa = gslot(sym_index(i, 0), 0) * BS; sb = gslot(sym_index(i, 1), 1) * BS; sc = gslot(sym_index(i, 2), 2) * BS;
+    sd = sa; se = sb;
+    wabc = rho_inv; wde = R(0); wc = R(0);
   }
-  const int eA = gslot(6 + qi, qj) * BS, eB = gslot(6 + qj, qi) * BS;
-  const int d0 = gslot(6, 0) * BS, d1 = gslot(7, 1) * BS, d2 = gslot(8, 2) * BS;
+  const int cs = (is_stress ? q : 0) * BS;     // coupling row read by this lane
 
   R qe[NBX];
 #pragma unroll
@@ -666,7 +696,7 @@ void k_level2(KPtrs p, LevelArgs a) {
   // ------------------------------------------------ surface: finish step n
   bool coup_pending = false;
   if constexpr (KIND != KIND_PREDICT) {
-    const int n = a.step_fin[cl];
+    const int n = step_fin_of(a, cl);
     const R* T1 = reinterpret_cast<const R*>(p.T1);
     const R* T2 = reinterpret_cast<const R*>(p.T2);
     const R* T3 = reinterpret_cast<const R*>(p.T3);
@@ -808,7 +838,7 @@ void k_level2(KPtrs p, LevelArgs a) {
   // The current derivative d^d Q lives only in the row exchange RX: each lane
   // writes its own modes of the next derivative there and reads them back for
   // the time integrals, so no register copy of it is kept across the loop.
-  const int nn = a.step_new[cl];
+  const int nn = step_new_of(a, cl);
   const int eflags = FI[12];
   const bool need_b2 = __syncthreads_or((eflags & EF_HAS_FINER) != 0);
   const int rec_slot = FI[15];
@@ -889,25 +919,14 @@ void k_level2(KPtrs p, LevelArgs a) {
       }
       __syncthreads();
     }
-    if (is_stress) {
 #pragma unroll
-      for (int lb = 0; lb < NBX; ++lb) {
-        const int b = base + lb;
-        if (lb < nb) {
-          const R cq = M > 0 ? coup[q * BS + b] : R(0);
-          if (M > 0) qe[lb] += c_d * cq;
-          if (more) {
-            const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
-            const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
-            rx[q * BS + b] = lam * delta * div + R(2) * mu * eps + cq;
-          }
-        }
-      }
-    } else if (more) {
-#pragma unroll
-      for (int lb = 0; lb < NBX; ++lb) {
-        const int b = base + lb;
-        if (lb < nb) rx[q * BS + b] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+    for (int lb = 0; lb < NBX; ++lb) {
+      const int b = base + lb;
+      if (lb < nb) {
+        const R cq = M > 0 ? wc * coup[cs + b] : R(0);
+        if (M > 0) qe[lb] += c_d * cq;
+        if (more)
+          rx[q * BS + b] = wabc * (grad[sa + b] + grad[sb + b] + grad[sc + b]) + wde * (grad[sd + b] + grad[se + b]) + cq;
       }
     }
   }
@@ -970,22 +989,11 @@ void k_level2(KPtrs p, LevelArgs a) {
       }
     }
   }
-  if (is_stress) {
 #pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) {
-      const int b = base + lb;
-      if (lb < nb) {
-        const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
-        const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
-        qe[lb] -= lam * delta * div + R(2) * mu * eps;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) {
-      const int b = base + lb;
-      if (lb < nb) qe[lb] -= rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
-    }
+  for (int lb = 0; lb < NBX; ++lb) {
+    const int b = base + lb;
+    if (lb < nb)
+      qe[lb] -= wabc * (grad[sa + b] + grad[sb + b] + grad[sc + b]) + wde * (grad[sd + b] + grad[se + b]);
   }
   if (need_b2) {   // B2 traces from the half-step integral (RX is free again)
 #pragma unroll
@@ -1053,7 +1061,7 @@ __global__ void k_sources(KPtrs p, LevelArgs a, SrcArgs s) {
   if (elem >= a.end) return;
   const int cl = cluster_of(a, elem);
   const double dt = a.dt[cl];
-  const int n = a.step_fin[cl];
+  const int n = step_fin_of(a, cl);
   const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
   const double w = stf_antiderivative(s.kind[src], s.par[2 * src], s.par[2 * src + 1], t1) -
                    stf_antiderivative(s.kind[src], s.par[2 * src], s.par[2 * src + 1], t0);
@@ -1078,7 +1086,7 @@ __global__ void k_receivers(KPtrs p, LevelArgs a, RecArgs r) {
   if (elem >= a.end) return;
   const int cl = cluster_of(a, elem);
   const double dt = a.dt[cl];
-  const int n = a.step_new[cl];
+  const int n = step_new_of(a, cl);
   const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
   const R* D = reinterpret_cast<const R*>(p.recD) + (size_t)r.slot[rec] * O * LPE * B;
   double val[O];
@@ -1104,6 +1112,16 @@ __global__ void k_receivers(KPtrs p, LevelArgs a, RecArgs r) {
 }
 
 }  // namespace
+
+// advance the device level clock by d finest steps (end of a cycle)
+__global__ void k_tick(long long* clock, long long d) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) clock[0] += d;
+}
+
+int launch_tick(long long* clock, long long d, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, clock, d);
+  return (int)hipGetLastError();
+}
 
 template <class R, int O, int M>
 int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st) {

@@ -50,8 +50,14 @@ struct LevelArgs {
   int n_clusters;
   int cl_end[MAX_CLUSTERS];     // padded end of cluster l (multiple of EPW)
   int cl_vend[MAX_CLUSTERS];    // end of cluster l's real elements (the rest is padding)
-  int step_fin[MAX_CLUSTERS];   // index of the step that ends at this level
-  int step_new[MAX_CLUSTERS];   // index of the step that starts at this level
+  // The level being processed is *clock + jrel (finest steps from t = 0; the
+  // clock is device memory so that a captured cycle can be replayed): at
+  // level G cluster l (active iff G is a multiple of 2^l) ends its step
+  // G/2^l - 1 and starts step G/2^l.  A start-of-advance prediction uses
+  // jrel = 0 at a synchronisation point.
+  const long long* clock;
+  int jrel;
+  int xcd_remap;     // 1: the workgroups of one XCD take a contiguous range of element groups
   double dt[MAX_CLUSTERS];
   double tc[MAX_CLUSTERS][MAX_ORDER];  // dt^{d+1}/(d+1)!
   double th[MAX_CLUSTERS][MAX_ORDER];  // (dt/2)^{d+1}/(d+1)!
@@ -82,6 +88,7 @@ struct RecArgs {
 
 template <class R, int O, int M>
 int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st);
+int launch_tick(long long* clock, long long d, hipStream_t st);
 template <class R, int O, int M>
 int launch_sources(const KPtrs& p, const LevelArgs& a, const SrcArgs& s, hipStream_t st);
 template <class R, int O, int M>
