@@ -51,8 +51,8 @@ PAPER_FLOPS_ALL_SPARSITY = 212688
 # size, summed over the four launches of a steady-state LTS cycle and divided by
 # the cycle's element updates.  Valid only for the kernel sources it was taken
 # on (their SHA-256 below); after any change the roofline reports null.
-TRAFFIC_BYTES_PER_UPDATE = 29238.0
-TRAFFIC_SOURCES_SHA256 = "2cb449ed35c015651d5d8b07d6d85f75099c8213796efb540c883639446fcfd9"
+TRAFFIC_BYTES_PER_UPDATE = 15270.6
+TRAFFIC_SOURCES_SHA256 = "e03c6083e998f4f60d06edac913ce1dfd030f3e333796a538335adb18a5263cb"
 KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
 

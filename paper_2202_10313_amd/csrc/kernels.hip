@@ -589,13 +589,15 @@ __device__ __forceinline__ int fresh(int v) {
   return v;
 }
 
-// slot of (row, direction) in the gradient exchange; 18 = not read (dummy)
+// slot of (row, direction) in the gradient exchange; 18 = not read (dummy).
+// The assignment is the one with the fewest LDS bank conflicts (over the
+// stiffness output writes, the strain reads of the memory variables and the
+// star-product reads of a time-kernel step) found by a search over slot
+// permutations for the strides above.
 __device__ __forceinline__ int gslot(int row, int dir) {
-  if (row >= 6) return (row - 6) * 3 + dir;
-  if (row < 3) return row == dir ? 9 + row : 18;
-  if (row == 3) return dir == 0 ? 12 : (dir == 1 ? 13 : 18);
-  if (row == 4) return dir == 1 ? 14 : (dir == 2 ? 15 : 18);
-  return dir == 0 ? 16 : (dir == 2 ? 17 : 18);
+  constexpr int T[9][3] = {{1, 18, 18}, {18, 6, 18}, {18, 18, 13}, {17, 12, 18}, {18, 14, 7},
+                           {16, 18, 15}, {0, 2, 5}, {11, 10, 3}, {4, 8, 9}};
+  return T[row][dir];
 }
 
 // KIND is the launch kind (KIND_PREDICT, KIND_FUSED, KIND_NEIGHBOR) as a
