@@ -695,6 +695,20 @@ void k_level2(KPtrs p, LevelArgs a) {
   for (int lb = 0; lb < NBX; ++lb)
     qe[lb] = lb < nb ? Qg[(base + lb) * NSLOT + slot] : R(0);
 
+  // memory variables of the owned modes, loaded early so that their latency
+  // overlaps the surface phase
+  R qa[JW][MM][6];
+#pragma unroll
+  for (int jw = 0; jw < JW; ++jw) {
+    const int lb = q + LPE * jw, b = base + lb;
+    const int jb = b / LPE;
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        qa[jw][l][c] = (M > 0 && lb < nb) ? Qag[((jb * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+  }
+
   // ------------------------------------------------ surface: finish step n
   bool coup_pending = false;
   if constexpr (KIND != KIND_PREDICT) {
@@ -742,7 +756,7 @@ void k_level2(KPtrs p, LevelArgs a) {
       }
     }
     __syncthreads();
-#pragma unroll 1
+#pragma unroll 2
     for (int rr = 0; rr < (4 * F + 2 * LPE - 1) / (2 * LPE); ++rr) {
       const int t = q + LPE * (w + 2 * rr);
       if (t < 4 * F) {
@@ -794,26 +808,16 @@ void k_level2(KPtrs p, LevelArgs a) {
     __syncthreads();
   }
 
-  R qa[JW][MM][6];
-  {
-  const int slotq = fresh(slot);
+  if (M > 0 && coup_pending) {
 #pragma unroll
-  for (int jw = 0; jw < JW; ++jw) {
-    const int lb = q + LPE * jw, b = base + lb;
-    const bool own = lb < nb;
-    const int jb = b / LPE;
+    for (int jw = 0; jw < JW; ++jw) {
+      const int lb = q + LPE * jw, b = base + lb;
+      if (lb < nb)
 #pragma unroll
-    for (int l = 0; l < MM; ++l)
+        for (int l = 0; l < MM; ++l)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        R v = R(0);
-        if (M > 0 && own) {
-          v = Qag[((jb * MM + l) * 6 + c) * NSLOT + slotq];
-          if (coup_pending) v += om[l] * coup[c * BS + b];
-        }
-        qa[jw][l][c] = v;
-      }
-  }
+          for (int c = 0; c < 6; ++c) qa[jw][l][c] += om[l] * coup[c * BS + b];
+    }
   }
   if (M > 0 && coup_pending) __syncthreads();
 
