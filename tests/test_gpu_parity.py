@@ -176,3 +176,57 @@ def test_error_codes():
     ctx.advance_to(s)
     with pytest.raises(EdgError):
         ctx.set_sources(np.array([[1e9, 0, 0]]), np.ones((1, 6)), 0, np.array([[2.0, 0.75]]))
+
+
+@pytest.mark.parametrize("order,fp64", [(3, True), (5, False)])
+def test_five_clusters(order, fp64):
+    """The maximum N_c = 5: a column of layers 20, 40, ..., 640 m thick fills
+    all five clusters (54 / 59 / 81 / 86 / 44 elements); one cycle is 16
+    finest levels.  Anelastic, with a source and receivers."""
+    mesh = synth.layered_box(3, 3, [20.0, 40.0, 80.0, 160.0, 320.0, 640.0], 1920.0, 1920.0, jitter=0.1, seed=5)
+    K = mesh["tet_verts"].shape[0]
+    mat = synth.homogeneous_materials(K, rho=2500.0, vp=3000.0, vs=1730.0, qp=173.0, qs=86.5)
+    attn = synth.attenuation_inputs(mat, 3, 0.1, 10.0)
+    w = dict(mesh=mesh, mat=mat, attn=attn)
+    src = synth.ricker_sources(31, 1, ((600.0, 1300.0), (600.0, 1300.0)), (30.0, 600.0), fc_range=(10.0, 10.0))
+    src["stf_params"][:, 1] = 0.01
+    rec = synth.surface_receivers(32, 4, ((200.0, 1700.0), (200.0, 1700.0)))
+    orc = Oracle(mesh, mat, order, attn=attn, n_clusters=5, lam=None, sources=src,
+                 receivers=dict(xyz=rec, dt_sample=2e-4, n_samples=400))
+    assert set(np.unique(orc.cl)) == {1, 2, 3, 4, 5}
+    ctx = gpu_context(w, order, 5, fp64)
+    assert np.array_equal(ctx.get_clusters()["clusters"], orc.cl)
+    q0 = synth.random_state(33, K, 27, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    ctx.set_sources(src["xyz"], src["moment"], src["stf_kind"], src["stf_params"])
+    ctx.set_receivers(rec, 2e-4, 400)
+    t = orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    e = parity(ctx.read_dofs(), orc.Q)
+    es = seis_parity(ctx.read_receivers(), orc.seis)
+    print(f"five clusters O={order} {'FP64' if fp64 else 'FP32'}: dofs {e:.3e} receivers {es:.3e}")
+    assert e <= (TOL64 if fp64 else TOL32) and es <= (TOL64 if fp64 else TOL32)
+
+
+@pytest.mark.parametrize("mechanisms", [0, 3])
+def test_order4_two_clusters_5k(mechanisms):
+    """The oracle-sized mesh of the differentiation workload: the 2 x 2 x 1 km
+    layered box (5,082 tets), O = 4, N_c = 2, FP32, elastic and anelastic."""
+    w = anelastic_setup("small", 4, 2, with_source=False)
+    K = w["mesh"]["tet_verts"].shape[0]
+    attn = w["attn"] if mechanisms else None
+    orc = Oracle(w["mesh"], w["mat"], 4, attn=attn, n_clusters=2, lam=None)
+    assert set(np.unique(orc.cl)) == {1, 2}
+    ctx = gpu_context(w, 4, 2, False, mechanisms=mechanisms)
+    nq = 9 + 6 * mechanisms
+    q0 = synth.random_state(34, K, nq, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    t = 2 * orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    e = parity(ctx.read_dofs(), orc.Q)
+    print(f"O=4 N_c=2 m={mechanisms} on {K} tets FP32: {e:.3e}")
+    assert e <= TOL32
