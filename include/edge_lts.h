@@ -132,6 +132,15 @@ int edg_get_clusters(const edg_ctx* ctx, int32_t* cluster_out, double* dt_min, d
  * at a synchronisation point (always true between calls). */
 int edg_set_initial(edg_ctx* ctx, int32_t run, const double* dofs);
 
+/* DOFs of selected elements of run `run`: ids [n] caller element indices
+ * (0..K-1; EDG_EINVAL otherwise), dofs / out [n][Nq][B] in the caller's vertex
+ * order; cap = doubles available in out.  Only the 7-element groups holding
+ * the elements are transferred, so a few elements of a large mesh are cheap to
+ * set or probe; other elements keep their values.  Repeated ids: the last one
+ * wins when setting. */
+int edg_set_dofs_subset(edg_ctx* ctx, int32_t run, int64_t n, const int64_t* ids, const double* dofs);
+int edg_read_dofs_subset(edg_ctx* ctx, int32_t run, int64_t n, const int64_t* ids, double* out, int64_t cap);
+
 /* Moment-tensor point sources of run `run` (0..n_runs-1): xyz [n][3], moment
  * [n][6] (xx,yy,zz,xy,yz,xz, N m), stf_params [n][2] (see EDG_STF_*).  Each
  * source adds -M phi(x_s)/|det J| times the exact integral of its moment rate

@@ -23,7 +23,7 @@ FLAG_GRAPH = 1
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = ["edg_create", "edg_upload_mesh", "edg_upload_materials", "edg_upload_clusters",
-           "edg_get_clusters", "edg_set_initial", "edg_set_sources", "edg_set_receivers",
+           "edg_get_clusters", "edg_set_initial", "edg_set_dofs_subset", "edg_read_dofs_subset", "edg_set_sources", "edg_set_receivers",
            "edg_advance_to", "edg_read_receivers", "edg_read_dofs", "edg_time", "edg_last_error",
            "edg_enable_timing", "edg_kernel_stats", "edg_element_updates", "edg_set_plan", "edg_get_plan",
            "edg_autotune", "edg_destroy", "edg_reference_matrices", "edg_cluster_host"]
@@ -70,6 +70,8 @@ def lib():
             "edg_upload_clusters": (ctypes.c_int, [_P, _P]),
             "edg_get_clusters": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
             "edg_set_initial": (ctypes.c_int, [_P, _I32, _P]),
+            "edg_set_dofs_subset": (ctypes.c_int, [_P, _I32, _I64, _P, _P]),
+            "edg_read_dofs_subset": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _I64]),
             "edg_set_sources": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _I32, _P]),
             "edg_set_receivers": (ctypes.c_int, [_P, _I64, _P, ctypes.c_double, _I64]),
             "edg_advance_to": (ctypes.c_int, [_P, ctypes.c_double]),
@@ -174,6 +176,17 @@ class Context:
     def set_initial(self, dofs, run=0):
         d = _f64(dofs, (self.K, self.nq, self.B))
         self._chk(self._L.edg_set_initial(self.h, run, _ptr(d)))
+
+    def set_dofs_subset(self, ids, dofs, run=0):
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        d = _f64(dofs, (len(ids), self.nq, self.B))
+        self._chk(self._L.edg_set_dofs_subset(self.h, run, len(ids), _ptr(ids), _ptr(d)))
+
+    def read_dofs_subset(self, ids, run=0):
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        out = np.empty((len(ids), self.nq, self.B))
+        self._chk(self._L.edg_read_dofs_subset(self.h, run, len(ids), _ptr(ids), _ptr(out), out.size))
+        return out
 
     def set_sources(self, xyz, moment, stf_kind, stf_params, run=0):
         xyz = _f64(xyz).reshape(-1, 3)

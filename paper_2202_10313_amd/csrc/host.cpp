@@ -401,6 +401,64 @@ int get_dofs_t(edg_ctx* c, int run, double* out) {
   return 0;
 }
 
+// DOFs of selected elements: only the 7-element groups that hold them are
+// copied (device -> host, and back when writing)
+template <class R>
+int subset_dofs_t(edg_ctx* c, int run, int64_t n, const int64_t* ids, const double* in, double* out) {
+  const int B = c->B, NQ = c->NQ, JB = jb_count(c);
+  const size_t qe_blk = (size_t)B * EPW * LPE;
+  const size_t qa_blk = c->M > 0 ? (size_t)JB * c->M * 6 * EPW * LPE : 0;
+  std::vector<int64_t> groups(n);
+  for (int64_t i = 0; i < n; ++i) groups[i] = c->user_to_internal[ids[i]] / EPW;
+  std::sort(groups.begin(), groups.end());
+  groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+  std::vector<R> he(groups.size() * qe_blk), ha(std::max<size_t>(groups.size() * qa_blk, 1));
+  R* const dqe = (R*)c->Qe.p + run * c->run_qe;
+  R* const dqa = (R*)c->Qa.p + run * c->run_qa;
+  for (size_t j = 0; j < groups.size(); ++j) {
+    HIPCHK(c, hipMemcpy(he.data() + j * qe_blk, dqe + groups[j] * qe_blk, qe_blk * sizeof(R), hipMemcpyDeviceToHost));
+    if (qa_blk)
+      HIPCHK(c, hipMemcpy(ha.data() + j * qa_blk, dqa + groups[j] * qa_blk, qa_blk * sizeof(R), hipMemcpyDeviceToHost));
+  }
+  std::vector<double> row(B);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = ids[i], ki = c->user_to_internal[k];
+    const size_t j = std::lower_bound(groups.begin(), groups.end(), ki / EPW) - groups.begin();
+    const int e = (int)(ki % EPW);
+    const auto& C = perm_matrix(c, c->perm[k]);
+    for (int q = 0; q < NQ; ++q) {
+      auto at = [&](int b) -> R& {
+        if (q < 9) return he[j * qe_blk + (size_t)b * (EPW * LPE) + e * LPE + q];
+        const int l = (q - 9) / 6, comp = (q - 9) % 6, jb = b / LPE, r = b % LPE;
+        return ha[j * qa_blk + ((size_t)(jb * c->M + l) * 6 + comp) * (EPW * LPE) + e * LPE + r];
+      };
+      if (in) {
+        const double* src = in + ((size_t)i * NQ + q) * B;
+        for (int b = 0; b < B; ++b) {
+          double sum = 0.0;
+          for (int bb = 0; bb < B; ++bb) sum += C[b * B + bb] * src[bb];
+          at(b) = R(sum);
+        }
+      } else {
+        for (int b = 0; b < B; ++b) row[b] = (double)at(b);
+        double* dst = out + ((size_t)i * NQ + q) * B;
+        for (int bb = 0; bb < B; ++bb) {
+          double sum = 0.0;
+          for (int b = 0; b < B; ++b) sum += C[b * B + bb] * row[b];
+          dst[bb] = sum;
+        }
+      }
+    }
+  }
+  if (in)
+    for (size_t j = 0; j < groups.size(); ++j) {
+      HIPCHK(c, hipMemcpy(dqe + groups[j] * qe_blk, he.data() + j * qe_blk, qe_blk * sizeof(R), hipMemcpyHostToDevice));
+      if (qa_blk)
+        HIPCHK(c, hipMemcpy(dqa + groups[j] * qa_blk, ha.data() + j * qa_blk, qa_blk * sizeof(R), hipMemcpyHostToDevice));
+    }
+  return 0;
+}
+
 // locate a point: lowest caller element index whose barycentrics are >= -tol
 int64_t locate(const edg_ctx* c, const double* x, double xi_sorted[3]) {
   const double tol = 1e-10;
@@ -862,6 +920,31 @@ int edg_read_dofs(edg_ctx* c, int32_t run, double* out, int64_t cap) {
   if (cap < c->K * c->NQ * c->B) return fail(c, EDG_ECAP, "output capacity too small");
   HIPCHK(c, hipSetDevice(c->cfg.device));
   return c->cfg.fp64 ? get_dofs_t<double>(c, run, out) : get_dofs_t<float>(c, run, out);
+}
+
+int edg_set_dofs_subset(edg_ctx* c, int32_t run, int64_t n, const int64_t* ids, const double* dofs) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (run < 0 || run >= c->runs || n < 0 || (n > 0 && (!ids || !dofs))) return fail(c, EDG_EINVAL, "bad arguments");
+  for (int64_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= c->K) return fail(c, EDG_EINVAL, "element index out of range");
+  if (n == 0) return EDG_OK;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  return c->cfg.fp64 ? subset_dofs_t<double>(c, run, n, ids, dofs, nullptr)
+                     : subset_dofs_t<float>(c, run, n, ids, dofs, nullptr);
+}
+
+int edg_read_dofs_subset(edg_ctx* c, int32_t run, int64_t n, const int64_t* ids, double* out, int64_t cap) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (run < 0 || run >= c->runs || n < 0 || (n > 0 && (!ids || !out))) return fail(c, EDG_EINVAL, "bad arguments");
+  if (cap < n * c->NQ * c->B) return fail(c, EDG_ECAP, "output capacity too small");
+  for (int64_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= c->K) return fail(c, EDG_EINVAL, "element index out of range");
+  if (n == 0) return EDG_OK;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  return c->cfg.fp64 ? subset_dofs_t<double>(c, run, n, ids, nullptr, out)
+                     : subset_dofs_t<float>(c, run, n, ids, nullptr, out);
 }
 
 int edg_set_sources(edg_ctx* c, int32_t run, int64_t n, const double* xyz, const double* moment, int32_t kind,

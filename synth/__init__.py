@@ -267,3 +267,142 @@ def loh_like_box(scale: str = "full", seed: int = 20) -> dict:
     if scale == "tiny":
         return layered_box(4, 4, [100.0] * 2 + [200.0] * 2, 1200.0, 1200.0, jitter=0.15, seed=seed)
     raise ValueError(scale)
+
+
+# --------------------------------------------------------------------------- graded basin workload
+
+def graded_box(xs, ys, zs, jitter: float = 0.0, seed: int = 0, top_bc: int = BC_FREE,
+               side_bc: int = BC_ABSORB) -> dict:
+    """Hex grid with the given (ascending) node coordinates per axis, Kuhn-split;
+    zs ascends from the bottom to 0.  Interior vertices are jittered by
+    +-jitter of the smaller adjacent spacing per axis; boundary vertices move
+    only along their boundary plane(s).  Top face z = max gets top_bc, the
+    other five side_bc."""
+    rng = np.random.default_rng(seed)
+    xs, ys, zs = (np.asarray(a, dtype=np.float64) for a in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+
+    def spacing(a):
+        d = np.diff(a)
+        return np.minimum(np.concatenate([[np.inf], d]), np.concatenate([d, [np.inf]]))
+
+    I, J, Kz = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    P = np.stack([xs[I], ys[J], zs[Kz]], axis=-1)
+    if jitter > 0:
+        d = rng.uniform(-jitter, jitter, size=P.shape)
+        d[..., 0] *= spacing(xs)[I]
+        d[..., 1] *= spacing(ys)[J]
+        d[..., 2] *= spacing(zs)[Kz]
+        d[..., 0][(I == 0) | (I == nx)] = 0.0
+        d[..., 1][(J == 0) | (J == ny)] = 0.0
+        d[..., 2][(Kz == 0) | (Kz == nz)] = 0.0
+        P = P + d
+    lat = _hex_grid_tets(nx, ny, nz)
+    ids = (lat[..., 0] * (ny + 1) + lat[..., 1]) * (nz + 1) + lat[..., 2]
+    xyz = P[lat[..., 0], lat[..., 1], lat[..., 2]]
+    bc = {(0, 0): side_bc, (0, 1): side_bc, (1, 0): side_bc, (1, 1): side_bc,
+          (2, 0): side_bc, (2, 1): top_bc}
+    face_bc = _tag_box_faces(lat, (nx, ny, nz), bc)
+    vol = np.einsum("ki,ki->k", np.cross(xyz[:, 1] - xyz[:, 0], xyz[:, 2] - xyz[:, 0]), xyz[:, 3] - xyz[:, 0])
+    ref = np.einsum("ki,ki->k", np.cross(lat[:, 1] - lat[:, 0], lat[:, 2] - lat[:, 0]).astype(float),
+                    (lat[:, 3] - lat[:, 0]).astype(float))
+    if np.any(np.sign(vol) != np.sign(ref)):
+        raise ValueError("jitter inverted a tetrahedron; lower it")
+    return dict(tet_verts=ids.astype(np.int64), tet_xyz=xyz, face_bc=face_bc,
+                box=np.array([[xs[0], xs[-1]], [ys[0], ys[-1]], [zs[0], zs[-1]]]), periodic=False)
+
+
+def radial_axis(n: int, h: float, s0: float, gmax: float, centred: bool) -> np.ndarray:
+    """Node coordinates of a uniform reference axis of n cells of size h mapped
+    by x = u min(1 + |u|/s0, gmax): cells grow away from u = 0 (the basin
+    centre, or the surface for the depth axis) up to a factor of about gmax."""
+    u = (np.arange(n + 1) - (n / 2 if centred else 0)) * h
+    return u * np.minimum(1.0 + np.abs(u) / s0, gmax)
+
+
+BASIN = {
+    # grid, reference spacing, grading, basin semi-axes [m]
+    "full": dict(n=(138, 138, 69), h=50.0, s0=250.0, gmax=10.0, axes=(8000.0, 6000.0, 2500.0)),
+    "small": dict(n=(14, 14, 7), h=50.0, s0=40.0, gmax=10.0, axes=(400.0, 300.0, 120.0)),
+}
+
+
+def basin_box(scale: str = "full", seed: int = 30) -> dict:
+    """One GPU's share of a high-frequency basin run: a uniform grid of 50 m
+    hexes graded radially about the basin centre at the surface (x = u min(1 +
+    |u|/s0, gmax) per axis, depth from the surface likewise), jitter 15%,
+    Kuhn-split.  'full': 138 x 138 x 69 cells (69 km x 69 km x 34.5 km),
+    K = 7,884,216; 'small': 14 x 14 x 7 cells with steeper grading and a
+    smaller basin, K = 8,232 (oracle-sized; both fill all five clusters)."""
+    p = BASIN[scale]
+    nx, ny, nz = p["n"]
+    xs = radial_axis(nx, p["h"], p["s0"], p["gmax"], True)
+    ys = radial_axis(ny, p["h"], p["s0"], p["gmax"], True)
+    zs = -radial_axis(nz, p["h"], p["s0"], p["gmax"], False)[::-1]
+    mesh = graded_box(xs, ys, zs, jitter=0.15, seed=seed)
+    mesh["basin_axes"] = np.array(p["axes"])
+    return mesh
+
+
+def basin_materials(mesh: dict, seed: int, sigma: float = 0.025, clip: float = 0.05) -> dict:
+    """Background vs(z) = 1500 + 3000 min(depth/12 km, 1)^0.6; inside the
+    ellipsoidal basin (semi-axes in mesh['basin_axes'], centred at the surface
+    origin) vs = 500 + 1000 e^2 with e the ellipsoidal radius; vp/vs = 2.0 at
+    vs = 500 falling linearly to 1.7 at vs = 4500; Gardner density; the
+    per-element Gaussian perturbation of the layered model; Qs = 50 vs[km/s],
+    Qp = 2 Qs."""
+    rng = np.random.default_rng(seed)
+    c = centroids(mesh)
+    depth = -c[:, 2]
+    vs = 1500.0 + 3000.0 * np.minimum(depth / 12000.0, 1.0) ** 0.6
+    a = mesh["basin_axes"]
+    e = np.sqrt((c[:, 0] / a[0]) ** 2 + (c[:, 1] / a[1]) ** 2 + (depth / a[2]) ** 2)
+    inside = e < 1.0
+    vs = np.where(inside, 500.0 + 1000.0 * e ** 2, vs)
+    ratio = np.clip(2.0 - 0.3 * (vs - 500.0) / 4000.0, 1.7, 2.0)
+    d = np.clip(rng.normal(0.0, sigma, len(vs)), -clip, clip)
+    vs = vs * (1.0 + d)
+    vp = ratio * vs
+    qs = 50.0 * vs / 1000.0
+    return dict(rho=gardner_rho(vp), vp=vp, vs=vs, qs=qs, qp=2.0 * qs)
+
+
+def double_couple(strike: float, dip: float, rake: float, M0: float) -> np.ndarray:
+    """Moment tensor (xx,yy,zz,xy,yz,xz) of a double couple, x east, y north,
+    z up, angles in radians (strike from north, clockwise)."""
+    # slip vector and fault normal in (east, north, up)
+    n = np.array([-math.sin(dip) * math.cos(strike), math.sin(dip) * math.sin(strike), math.cos(dip)])
+    s = np.array([math.cos(rake) * math.sin(strike) - math.sin(rake) * math.cos(dip) * math.cos(strike),
+                  math.cos(rake) * math.cos(strike) + math.sin(rake) * math.cos(dip) * math.sin(strike),
+                  math.sin(rake) * math.sin(dip)])
+    M = M0 * (np.outer(s, n) + np.outer(n, s))
+    return np.array([M[0, 0], M[1, 1], M[2, 2], M[0, 1], M[1, 2], M[0, 2]])
+
+
+def kinematic_fault(seed: int, centre, length: float = 10000.0, width: float = 10000.0, n_along: int = 20,
+                    n_down: int = 20, mu: float = 3.0e10, vr: float = 2800.0) -> dict:
+    """Planar finite source of n_along x n_down double-couple subfaults with
+    Hann moment rates: seeded strike, dip and rake; rupture time = distance
+    from a seeded hypocentre / vr; rise time U[0.5, 1.5] s; peak slip rate
+    U[0.5, 1.5] m/s (slip = peak rate x rise / 2, moment = mu x area x slip).
+    stf_params rows are [t0, T] (Hann)."""
+    rng = np.random.default_rng(seed)
+    strike = rng.uniform(0.0, 2.0 * math.pi)
+    dip = rng.uniform(math.radians(45.0), math.radians(85.0))
+    rake = rng.uniform(-math.pi, math.pi)
+    along = np.array([math.sin(strike), math.cos(strike), 0.0])
+    down = np.cross(along, np.array([-math.sin(dip) * math.cos(strike), math.sin(dip) * math.sin(strike),
+                                     math.cos(dip)]))
+    if down[2] > 0:
+        down = -down
+    a = (np.arange(n_along) + 0.5) / n_along - 0.5
+    b = (np.arange(n_down) + 0.5) / n_down - 0.5
+    A, Bd = np.meshgrid(a * length, b * width, indexing="ij")
+    xyz = np.asarray(centre)[None, :] + A.reshape(-1, 1) * along[None, :] + Bd.reshape(-1, 1) * down[None, :]
+    hypo = xyz[rng.integers(len(xyz))]
+    t0 = np.linalg.norm(xyz - hypo, axis=1) / vr
+    rise = rng.uniform(0.5, 1.5, len(xyz))
+    slip = rng.uniform(0.5, 1.5, len(xyz)) * rise / 2.0
+    area = (length / n_along) * (width / n_down)
+    moment = np.stack([double_couple(strike, dip, rake, mu * area * s) for s in slip])
+    return dict(xyz=xyz, moment=moment, stf_kind=STF_HANN, stf_params=np.stack([t0, rise], axis=1))

@@ -11,3 +11,16 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _torch_initialises_hip_first(request):
+    """Tests that hand torch's stream to the library need torch and the library
+    on one HIP runtime, and torch only initialises it if it comes first: when
+    GPU tests are selected, initialise torch's device before any test loads
+    the library."""
+    if any(item.get_closest_marker("gpu") for item in request.session.items):
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    yield
