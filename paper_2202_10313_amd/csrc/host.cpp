@@ -49,6 +49,14 @@ struct edg_ctx {
 
   std::vector<double> rho, vp, vs, yp, ys, omega;
 
+  struct Locator {              // bucket grid for point location
+    bool ready = false;
+    double lo[3], hi[3], h[3];
+    int n[3];
+    std::vector<size_t> start;  // [cells + 1]
+    std::vector<int64_t> elem;
+  } loc;
+
   std::vector<int> cl;  // 0-based cluster per caller element
   double dt_min = 0, lam = 1, speedup = 1;
   // internal order: clusters finest first, each cluster's range starting on a
@@ -460,19 +468,75 @@ int subset_dofs_t(edg_ctx* c, int run, int64_t n, const int64_t* ids, const doub
 }
 
 // locate a point: lowest caller element index whose barycentrics are >= -tol
-int64_t locate(const edg_ctx* c, const double* x, double xi_sorted[3]) {
-  const double tol = 1e-10;
-  for (int64_t k = 0; k < c->K; ++k) {
+// bucket grid over the element bounding boxes (built on the first query):
+// every element is listed, in ascending index, in each cell its padded box
+// touches
+void build_locator(edg_ctx* c) {
+  auto& L = c->loc;
+  const int64_t K = c->K;
+  for (int d = 0; d < 3; ++d) {
+    L.lo[d] = 1e300;
+    L.hi[d] = -1e300;
+  }
+  std::vector<double> box((size_t)K * 6);
+  for (int64_t k = 0; k < K; ++k) {
     const double* X = &c->X[(size_t)k * 12];
-    double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
-      lo[d] = std::min(std::min(X[d], X[3 + d]), std::min(X[6 + d], X[9 + d]));
-      hi[d] = std::max(std::max(X[d], X[3 + d]), std::max(X[6 + d], X[9 + d]));
-      const double pad = 1e-9 * (hi[d] - lo[d] + 1.0);
-      lo[d] -= pad;
-      hi[d] += pad;
+      double lo = std::min(std::min(X[d], X[3 + d]), std::min(X[6 + d], X[9 + d]));
+      double hi = std::max(std::max(X[d], X[3 + d]), std::max(X[6 + d], X[9 + d]));
+      const double pad = 1e-9 * (hi - lo + 1.0);
+      lo -= pad;
+      hi += pad;
+      box[(size_t)k * 6 + d] = lo;
+      box[(size_t)k * 6 + 3 + d] = hi;
+      L.lo[d] = std::min(L.lo[d], lo);
+      L.hi[d] = std::max(L.hi[d], hi);
     }
-    if (x[0] < lo[0] || x[0] > hi[0] || x[1] < lo[1] || x[1] > hi[1] || x[2] < lo[2] || x[2] > hi[2]) continue;
+  }
+  const int n = std::max(1, (int)std::cbrt((double)K / 4.0));
+  for (int d = 0; d < 3; ++d) {
+    L.n[d] = n;
+    L.h[d] = (L.hi[d] - L.lo[d]) / n;
+    if (!(L.h[d] > 0)) L.h[d] = 1.0;
+  }
+  auto cell = [&](int d, double v) { return std::min(L.n[d] - 1, std::max(0, (int)((v - L.lo[d]) / L.h[d]))); };
+  const size_t ncell = (size_t)n * n * n;
+  L.start.assign(ncell + 1, 0);
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int64_t> fill;
+    if (pass == 1) {
+      for (size_t i = 0; i < ncell; ++i) L.start[i + 1] += L.start[i];
+      L.elem.resize(L.start[ncell]);
+      fill.assign(L.start.begin(), L.start.end() - 1);
+    }
+    for (int64_t k = 0; k < K; ++k) {
+      const double* b = &box[(size_t)k * 6];
+      for (int i = cell(0, b[0]); i <= cell(0, b[3]); ++i)
+        for (int j = cell(1, b[1]); j <= cell(1, b[4]); ++j)
+          for (int l = cell(2, b[2]); l <= cell(2, b[5]); ++l) {
+            const size_t ci = ((size_t)i * n + j) * n + l;
+            if (pass == 0) L.start[ci + 1]++;
+            else L.elem[fill[ci]++] = k;
+          }
+    }
+  }
+  L.ready = true;
+}
+
+// locate a point: lowest caller element index whose barycentrics are >= -tol
+int64_t locate(edg_ctx* c, const double* x, double xi_sorted[3]) {
+  const double tol = 1e-10;
+  if (!c->loc.ready) build_locator(c);
+  const auto& L = c->loc;
+  int idx[3];
+  for (int d = 0; d < 3; ++d) {
+    if (!(x[d] >= L.lo[d] && x[d] <= L.hi[d])) return -1;
+    idx[d] = std::min(L.n[d] - 1, std::max(0, (int)((x[d] - L.lo[d]) / L.h[d])));
+  }
+  const size_t ci = ((size_t)idx[0] * L.n[1] + idx[1]) * L.n[2] + idx[2];
+  for (size_t e = L.start[ci]; e < L.start[ci + 1]; ++e) {
+    const int64_t k = L.elem[e];
+    const double* X = &c->X[(size_t)k * 12];
     const double* G = &c->Gm[(size_t)k * 9];
     double r[3];
     for (int cc = 0; cc < 3; ++cc) {
@@ -670,6 +734,7 @@ int edg_upload_mesh(edg_ctx* c, int64_t K, const int64_t* tv, const double* xyz,
   if (K <= 0 || !tv || !xyz) return fail(c, EDG_EINVAL, "empty mesh or null arrays");
   if (K > (int64_t)0x7fffffff / 8) return fail(c, EDG_EINVAL, "too many tets");
   c->K = K;
+  c->loc = edg_ctx::Locator{};
   c->perm.assign(K, {0, 1, 2, 3});
   c->nbr.assign(K * 4, -1);
   c->nbr_face.assign(K * 4, -1);

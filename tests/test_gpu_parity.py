@@ -230,3 +230,35 @@ def test_order4_two_clusters_5k(mechanisms):
     e = parity(ctx.read_dofs(), orc.Q)
     print(f"O=4 N_c=2 m={mechanisms} on {K} tets FP32: {e:.3e}")
     assert e <= TOL32
+
+
+def test_receivers_on_shared_vertices_and_faces():
+    """Receivers exactly on vertices and face centroids shared by several
+    tets go to the lowest element index (DG fields differ between the
+    elements, so a different choice would show in the seismograms)."""
+    w = anelastic_setup("tiny", 3, 3, with_source=False)
+    mesh = w["mesh"]
+    K = mesh["tet_verts"].shape[0]
+    # interior vertices (not on the box boundary) and interior face centroids
+    verts = mesh["tet_xyz"].reshape(-1, 3)
+    box = mesh["box"]
+    inner = np.all((verts > box[:, 0] + 1.0) & (verts < box[:, 1] - 1.0), axis=1)
+    pts = [verts[np.nonzero(inner)[0][i * 37]] for i in range(4)]
+    nbr = __import__("helpers").face_adjacency(mesh["tet_verts"])
+    for k in (30, 150, 301):   # faces whose other element has the lower index
+        i = int(np.nonzero((nbr[k] >= 0) & (nbr[k] < k))[0][0])
+        pts.append(mesh["tet_xyz"][k][[m for m in range(4) if m != i]].mean(axis=0))
+    rec = np.array(pts)
+    orc = Oracle(mesh, w["mat"], 3, attn=w["attn"], n_clusters=3, lam=None,
+                 receivers=dict(xyz=rec, dt_sample=3.7e-4, n_samples=80))
+    ctx = gpu_context(w, 3, 3, True)
+    q0 = synth.random_state(40, K, 27, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    ctx.set_receivers(rec, 3.7e-4, 80)
+    t = 2 * orc.sync_dt
+    orc.run(t)
+    ctx.advance_to(t)
+    es = seis_parity(ctx.read_receivers(), orc.seis)
+    print(f"receivers on shared vertices / faces: {es:.3e}")
+    assert es <= TOL64
