@@ -179,3 +179,81 @@ def godunov_matrices(An_m, An_p, n, kind):
         proj = Rin[absorb] @ np.linalg.solve(P, np.transpose(Lin, (0, 2, 1)))
         Gm[absorb] = I9[absorb] - proj
     return Gm, Gp
+
+
+def flux_matrices_closed(n, rho, vp, vs, rho_n, vp_n, vs_n, kind, omega):
+    """The element's face flux A_n q*- as Fm q- + Fp q+ (Fm, Fp [F, nq, 9]),
+    written from the impedance form of the same Godunov state instead of
+    eigenvectors, so that it is analytic in the materials and can be
+    differentiated by complex steps (used for the adjoint's material
+    derivatives; pinned against godunov_matrices in tests/test_oracle_adjoint.py).
+
+    Normal and tangential parts of the interface velocity v* and traction t*
+    for impedances Z = rho vp (normal) and rho vs (tangential) on each side:
+      v* = (Z- v- + Z+ v+ + t+ - t-) / (Z- + Z+)
+      t* = (Z+ t- + Z- t+ + Z- Z+ (v+ - v-)) / (Z- + Z+).
+    Free surface: outside state (-t-, v-); absorbing: outside state 0; both
+    with the element's own impedances.  A_n applied to a state depends only on
+    its traction and velocity:
+      stress (i,j):   -(lambda delta_ij n.v* + mu (n_i v*_j + n_j v*_i))
+      velocity i:     -t*_i / rho
+      memory (l,i,j): -omega_l (n_i v*_j + n_j v*_i) / 2."""
+    n = np.asarray(n, dtype=np.float64)
+    F = n.shape[0]
+    m = len(omega)
+    nq = n_quantities(m)
+    kind = np.asarray(kind)
+    rho, vp, vs, rho_n, vp_n, vs_n = (np.asarray(a) for a in (rho, vp, vs, rho_n, vp_n, vs_n))
+    inner = kind == 0
+    # outside material: own for boundaries
+    rho_o = np.where(inner, rho_n, rho)
+    vp_o = np.where(inner, vp_n, vp)
+    vs_o = np.where(inner, vs_n, vs)
+    zpm, zsm = rho * vp, rho * vs
+    zpp, zsp = rho_o * vp_o, rho_o * vs_o
+    lam = rho * vp * vp - 2.0 * rho * vs * vs
+    mu = rho * vs * vs
+    Tr = traction_op(n)                                  # [F,3,9]
+    Vl = velocity_op(F)
+    Pn = n[:, :, None] * n[:, None, :]                   # [F,3,3]
+    Pt = np.eye(3)[None] - Pn
+
+    def mix(a, b):   # P_n a_n + P_t a_t for per-face scalars a (normal), b (tangential)
+        return Pn * a[:, None, None] + Pt * b[:, None, None]
+
+    ip, is_ = 1.0 / (zpm + zpp), 1.0 / (zsm + zsp)
+    # v* = Cvv- v- + Cvt- t- + Cvv+ v+ + Cvt+ t+ ; t* likewise
+    Cvvm, Cvtm = mix(zpm * ip, zsm * is_), mix(-ip, -is_)
+    Cvvp, Cvtp = mix(zpp * ip, zsp * is_), mix(ip, is_)
+    Cttm, Ctvm = mix(zpp * ip, zsp * is_), mix(-zpm * zpp * ip, -zsm * zsp * is_)
+    Cttp, Ctvp = mix(zpm * ip, zsm * is_), mix(zpm * zpp * ip, zsm * zsp * is_)
+    # outside state as a map of the inside one for the boundaries
+    free = (kind == 1)[:, None, None]
+    absorb = (kind == 2)[:, None, None]
+    # free: t+ = -t-, v+ = v-  -> fold into the minus-side maps
+    Cvvm = Cvvm + np.where(free, Cvvp, 0.0)
+    Cvtm = Cvtm - np.where(free, Cvtp, 0.0)
+    Cttm = Cttm - np.where(free, Cttp, 0.0)
+    Ctvm = Ctvm + np.where(free, Ctvp, 0.0)
+    bnd = free | absorb
+    Cvvp, Cvtp = np.where(bnd, 0.0, Cvvp), np.where(bnd, 0.0, Cvtp)
+    Cttp, Ctvp = np.where(bnd, 0.0, Cttp), np.where(bnd, 0.0, Ctvp)
+    Vm = Cvvm @ Vl + Cvtm @ Tr                           # v* from q- [F,3,9]
+    Vp = Cvvp @ Vl + Cvtp @ Tr
+    Tm = Cttm @ Tr + Ctvm @ Vl                           # t* from q-
+    Tp = Cttp @ Tr + Ctvp @ Vl
+    # flux rows as maps of (v*, t*)
+    Fv = np.zeros((F, nq, 3), dtype=np.result_type(lam, n))
+    Ft = np.zeros((F, nq, 3), dtype=np.result_type(rho, n))
+    SYMP = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+    for q, (i, j) in enumerate(SYMP):
+        for k in range(3):
+            c = -(lam * (i == j) * n[:, k] + mu * ((i == k) * n[:, j] + (j == k) * n[:, i]))
+            Fv[:, q, k] = c
+            for l in range(m):
+                Fv[:, 9 + 6 * l + q, k] = -omega[l] * 0.5 * ((i == k) * n[:, j] + (j == k) * n[:, i])
+    for i in range(3):
+        Ft[:, VEL + i, i] = -1.0 / rho
+    Fm = Fv @ Vm + Ft @ Tm
+    Fp = Fv @ Vp + Ft @ Tp
+    return Fm, Fp
