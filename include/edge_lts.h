@@ -199,6 +199,45 @@ int edg_get_plan(const edg_ctx* ctx, edg_plan* plan);
  * may be NULL.  The tuning cycles are left out of edg_kernel_stats. */
 int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cycle);
 
+/* ---- discrete adjoint -------------------------------------------------------
+ * The paper names full-waveform inversion as a use of the solver (Sec. I
+ * (Introduction)) without an adjoint; these calls give the exact transpose of
+ * the discrete LTS scheme of Sec. III-A (Discrete Formulation) and Sec. V-B
+ * (Buffers and Algorithm) as this library computes it, for gradients of
+ * receiver misfits with respect to per-element rho, vp and vs.  Time steps,
+ * clusters, omega and the anelastic weights Yp, Ys are held fixed.  Single
+ * run contexts only (n_runs = 1). */
+
+/* every_cycles > 0: from now on edg_advance_to splits its cycles into
+ * segments of at most every_cycles cycles and stores the state (device
+ * memory, K x Nq x B words each) at the start of every segment; 0 turns it
+ * off.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a negative
+ * interval.  The checkpoints are dropped again by edg_set_initial,
+ * edg_set_dofs_subset, edg_upload_materials, edg_upload_clusters,
+ * edg_set_sources and edg_rewind. */
+int edg_set_checkpointing(edg_ctx* ctx, int32_t every_cycles);
+
+/* Back to t = 0: DOFs, buffers and recorded seismograms are zeroed;
+ * materials, clusters, time steps, sources and receivers stay.  With
+ * edg_upload_materials (which keeps clusters and time steps) this re-runs a
+ * simulation for perturbed materials. */
+int edg_rewind(edg_ctx* ctx);
+
+/* Reverse sweep over the advance since the first checkpoint: with the
+ * derivative of a scalar misfit J with respect to the recorded seismogram
+ * samples, dj_dseis [n_rec][n_samples][9] (the layout of edg_read_receivers;
+ * NULL = 0), and with respect to the current DOFs, dj_dq [K][Nq][B] (caller
+ * order; NULL = 0), writes dJ/d(DOFs at the first checkpoint) to g_q0
+ * [K][Nq][B] and dJ/d rho, dJ/d vp, dJ/d vs [K] to g_rho, g_vp, g_vs (any may
+ * be NULL).  Each segment is replayed forward from its checkpoint (the states
+ * at the start of every level are kept in device memory, (levels per
+ * segment) x K x Nq x B words), then its levels run backwards through the
+ * adjoint kernels.  All host arrays are caller-owned and only read or written
+ * during the call; the DOFs and the time are those of before the call when it
+ * returns.  EDG_ESTATE without checkpoints or for n_runs > 1. */
+int edg_adjoint(edg_ctx* ctx, const double* dj_dseis, const double* dj_dq, double* g_q0, double* g_rho,
+                double* g_vp, double* g_vs);
+
 /* Destroy the context and free its device memory (NULL is ignored). */
 void edg_destroy(edg_ctx* ctx);
 
@@ -215,6 +254,17 @@ int edg_reference_matrices(int32_t order, double* K, double* Ft);
  * lambda_in <= 0 searches. */
 int edg_cluster_host(int64_t K, const double* dt, const int64_t* nbr, int32_t n_clusters,
                      double lambda_in, int32_t* cluster, double* lambda_out, double* speedup_out);
+
+/* The Godunov face flux of one face mode and its reverse mode (FP64 on the
+ * host), as the kernels evaluate them: bc 0 interior, 1 free surface, 2
+ * absorbing; qm, qp [9] inside / outside traces; prm = (nx, ny, nz, Zp-, Zs-,
+ * Zp+, Zs+, lam, mu, 1/rho, s) with s = 2|S_i| / |det J|; writes out [15]
+ * (9 elastic rows, 6 strain-rate rows of the memory variables, unscaled by
+ * omega), and for the output adjoint u [15]: qm_b, qp_b [9] (transposed
+ * flux maps) and pb [7] (derivatives of u . out in 1/rho, lam, mu, Zp-,
+ * Zs-, Zp+, Zs+).  Returns -1 for bad arguments. */
+int edg_godunov_host(int32_t bc, const double* qm, const double* qp, const double* prm, const double* u,
+                     double* out, double* qm_b, double* qp_b, double* pb);
 
 #ifdef __cplusplus
 }

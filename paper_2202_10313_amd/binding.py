@@ -26,7 +26,8 @@ EXPORTS = ["edg_create", "edg_upload_mesh", "edg_upload_materials", "edg_upload_
            "edg_get_clusters", "edg_set_initial", "edg_set_dofs_subset", "edg_read_dofs_subset", "edg_set_sources", "edg_set_receivers",
            "edg_advance_to", "edg_read_receivers", "edg_read_dofs", "edg_time", "edg_last_error",
            "edg_enable_timing", "edg_kernel_stats", "edg_element_updates", "edg_set_plan", "edg_get_plan",
-           "edg_autotune", "edg_destroy", "edg_reference_matrices", "edg_cluster_host"]
+           "edg_autotune", "edg_set_checkpointing", "edg_rewind", "edg_adjoint", "edg_destroy",
+           "edg_reference_matrices", "edg_cluster_host", "edg_godunov_host"]
 
 
 class EdgError(RuntimeError):
@@ -85,9 +86,13 @@ def lib():
             "edg_set_plan": (ctypes.c_int, [_P, _P]),
             "edg_get_plan": (ctypes.c_int, [_P, _P]),
             "edg_autotune": (ctypes.c_int, [_P, _I32, _P, _P]),
+            "edg_set_checkpointing": (ctypes.c_int, [_P, _I32]),
+            "edg_rewind": (ctypes.c_int, [_P]),
+            "edg_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
             "edg_destroy": (None, [_P]),
             "edg_reference_matrices": (ctypes.c_int, [_I32, _P, _P]),
             "edg_cluster_host": (ctypes.c_int, [_I64, _P, _P, _I32, ctypes.c_double, _P, _P, _P]),
+            "edg_godunov_host": (ctypes.c_int, [_I32, _P, _P, _P, _P, _P, _P, _P, _P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -238,6 +243,23 @@ class Context:
         self._chk(self._L.edg_get_plan(self.h, ctypes.byref(pl)))
         return pl.as_dict()
 
+    # --- discrete adjoint
+    def set_checkpointing(self, every_cycles):
+        self._chk(self._L.edg_set_checkpointing(self.h, int(every_cycles)))
+
+    def rewind(self):
+        self._chk(self._L.edg_rewind(self.h))
+
+    def adjoint(self, dj_dseis=None, dj_dq=None, want_q0=True):
+        """Reverse sweep since the first checkpoint: returns dict(q0_b, g_rho,
+        g_vp, g_vs) for the given misfit derivatives (None = 0)."""
+        sb = None if dj_dseis is None else _f64(dj_dseis, (self.n_rec, self.n_samples, 9))
+        qb = None if dj_dq is None else _f64(dj_dq, (self.K, self.nq, self.B))
+        q0 = np.empty((self.K, self.nq, self.B)) if want_q0 else None
+        g = [np.empty(self.K) for _ in range(3)]
+        self._chk(self._L.edg_adjoint(self.h, _ptr(sb), _ptr(qb), _ptr(q0), *[_ptr(a) for a in g]))
+        return dict(q0_b=q0, g_rho=g[0], g_vp=g[1], g_vs=g[2])
+
     def autotune(self, cycles=1):
         """Advance `cycles` LTS cycles per candidate plan and keep the fastest;
         returns (plan, kernel ms per cycle of that plan)."""
@@ -245,6 +267,18 @@ class Context:
         ms = ctypes.c_double()
         self._chk(self._L.edg_autotune(self.h, int(cycles), ctypes.byref(pl), ctypes.byref(ms)))
         return pl.as_dict(), ms.value
+
+
+def godunov_host(bc, qm, qp, prm, u):
+    """Face flux of one mode and its reverse mode (host FP64): returns
+    (out [15], qm_b [9], qp_b [9], pb [7])."""
+    qm, qp, prm, u = _f64(qm), _f64(qp), _f64(prm), _f64(u)
+    out, qmb, qpb, pb = np.empty(15), np.empty(9), np.empty(9), np.empty(7)
+    rc = lib().edg_godunov_host(int(bc), _ptr(qm), _ptr(qp), _ptr(prm), _ptr(u), _ptr(out), _ptr(qmb), _ptr(qpb),
+                                _ptr(pb))
+    if rc != EDG_OK:
+        raise EdgError(rc, "edg_godunov_host")
+    return out, qmb, qpb, pb
 
 
 def reference_matrices(order):

@@ -42,7 +42,8 @@ def build(verbose: bool = False) -> str:
     _run(["g++", "-O2", "-std=c++17", "-o", gen, os.path.join(CSRC, "gen_refmats.cpp"),
           os.path.join(CSRC, "basis.cpp")])
     _run([gen, os.path.join(CSRC, "generated", "refmats.h")] + ORDERS)
-    units = [("kernels.hip", "kernels.o"), ("host.cpp", "host.o"), ("basis.cpp", "basis.o")]
+    units = [("kernels.hip", "kernels.o"), ("adjoint.hip", "adjoint.o"), ("host.cpp", "host.o"),
+             ("basis.cpp", "basis.o")]
 
     def compile_unit(u):
         src, obj = u
@@ -50,7 +51,7 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC] + HIPFLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)])
         return obj
 
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(compile_unit, units))
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [os.path.join(BUILD, o) for o in objs])

@@ -1,0 +1,770 @@
+// HIP kernels (gfx950) of the discrete adjoint of the clustered rate-2 LTS
+// ADER-DG update: the exact transpose of the forward kernels' arithmetic, for
+// gradients of receiver misfits with respect to the materials.  The paper
+// names inversion as a use (Sec. I (Introduction)) but gives no adjoint; the
+// forward scheme it transposes is that of Sec. III-A (Discrete Formulation)
+// and Sec. V-B (Buffers and Algorithm).
+//
+// The forward advance is a sequence of per-level launches: at finest level j
+// the clusters whose step ends there finish it (surface update from the own
+// B1 face trace and the neighbour data), then the clusters whose step starts
+// there predict (time kernel, B1/B2/B3 traces, volume update).  The adjoint
+// runs the levels backwards and, per level, first the transposed predictions
+// (KIND_ADJ_PREDICT), then the transposed neighbour-data updates
+// (KIND_ADJ_UPDATE), in two launches.
+//
+//  * ADJ_UPDATE (element k, step n ending at this level): the adjoint Qbar of
+//    k does not change (the update is Q += ...); what flows out are the face
+//    adjoints u = trace(Qbar) (9 elastic rows and the 6 omega-weighted sums of
+//    the memory-variable rows, 15 x F per face), added to the slot the
+//    neighbour across the face keeps for the buffer k read: same cluster ->
+//    its B1 slot; coarser neighbour -> its B2 slot in the first half of its
+//    step, B1 slot and minus B2 slot in the second; finer neighbour -> its B3
+//    slot.  Each slot has one writer (the element across the face).
+//  * ADJ_PREDICT (element j, step n starting here): recomputes the time
+//    derivatives from the stored start-of-step state, then forms the adjoint
+//    of the time integrals: the transposed volume kernel and own surface part
+//    (from Qbar), plus the slots its neighbours filled, each pulled through
+//    the transpose of the neighbour's flux (Godunov with the neighbour's
+//    parameters); then runs the Cauchy-Kowalevski recursion backwards and adds
+//    the adjoint of the start-of-step state to Qbar.  It clears the slots it
+//    consumed (B3 after its even step, the first of the pair the coarser
+//    neighbour read as one sum).
+//
+// Material derivatives: every product that involves a material parameter
+// (lam, mu, 1/rho, a_l, b_l, the impedances of the flux solver) adds its
+// adjoint-weighted partial derivative to per-element FP64 words (NG); the
+// host applies the chain rule to rho, vp, vs.
+//
+// Work mapping as in the forward k_level: one wave of 64 lanes owns 7
+// elements, lane 9e + q holds row q of element e for all modes and the memory
+// variables of the modes q + 9 jb; reference-matrix products are the
+// generated straight-line code and its transposes; row-mixing products go
+// through LDS.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "generated/refmats.h"
+#include "kernels.hpp"
+#include "device_common.hpp"
+
+namespace edg {
+
+namespace {
+
+template <class R, int O, int M>
+struct AdjLds {
+  using RF = edg_gen::Ref<O>;
+  static constexpr int B = RF::B, FP = RF::FP;
+  static constexpr int U = 0;                               // face adjoints [face][15][FP]
+  static constexpr int PM = 4 * ADJ_ROWS * FP;              // traces / their adjoints [face][9][FP]
+  static constexpr int FACE = PM + 4 * LPE * FP;
+  static constexpr int GRD = 0;                             // gradients [row][dir][b]
+  static constexpr int X = LPE * 3 * B;                     // rows [row][b]
+  static constexpr int C = X + LPE * B;                     // stress components [c][b]
+  static constexpr int MODE = C + 6 * B;
+  static constexpr int REGION = FACE > MODE ? FACE : MODE;
+  static constexpr int TOTAL = EPW * REGION;
+};
+
+// adds v to the element's gradient word w (LDS, FP64)
+__device__ __forceinline__ void gadd(double* gs, int w, double v) { atomicAdd(gs + w, v); }
+
+template <class R, int O, int M>
+__global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
+  using RF = edg_gen::Ref<O>;
+  using L = AdjLds<R, O, M>;
+  constexpr int B = RF::B, F = RF::F, FP = RF::FP;
+  constexpr int MM = M > 0 ? M : 1;
+  constexpr int JB = (B + LPE - 1) / LPE;
+  __shared__ R lds[L::TOTAL];
+  __shared__ double gsh[EPW * NG];
+
+  const int lane = threadIdx.x;
+  const int e = lane / LPE, r = lane % LPE;
+  const bool act = e < EPW;                 // lane 63 computes a copy of lane 54 and never writes
+  const int ec = act ? e : EPW - 1;
+  const int q = act ? r : 0;
+  const int g = blockIdx.x;
+  const int elem = g * EPW + ec;
+  const int cl = cluster_of(a, g * EPW);
+  const bool valid = act && (elem < a.cl_vend[cl]);
+  const int slot = ec * LPE + q;
+  R* const reg = lds + ec * L::REGION;
+  double* const gs = gsh + ec * NG;
+  const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
+  const int* FI = p.FI + (size_t)elem * FI_WORDS;
+  R* const Le = reinterpret_cast<R*>(ad.Le);
+  R* const La = reinterpret_cast<R*>(ad.La);
+  const size_t sstride = (size_t)4 * ADJ_ROWS * FP;         // per element in a slot array
+
+  const bool is_stress = q < 6;
+  int qi = 0, qj = 0;
+  if (q < 3) { qi = q; qj = q; }
+  else if (q == 3) { qi = 0; qj = 1; }
+  else if (q == 4) { qi = 1; qj = 2; }
+  else if (q == 5) { qi = 0; qj = 2; }
+  const R delta = q < 3 ? R(1) : R(0);
+
+  R G[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) G[c] = P[c];
+  const R rho_inv = P[9], lam = P[10], mu = P[11], zp = P[12], zs = P[13];
+  R al[MM], bl[MM], om[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    al[l] = M > 0 ? P[14 + 2 * l] : R(0);
+    bl[l] = M > 0 ? P[15 + 2 * l] : R(0);
+    om[l] = M > 0 ? R(a.omega[l]) : R(0);
+  }
+
+  // adjoint state: this lane's elastic row, the memory variables of its modes
+  R le[B];
+  R la[JB][MM][6];
+  const size_t gbase = (size_t)g * B;
+#pragma unroll
+  for (int b = 0; b < B; ++b) le[b] = Le[(gbase + b) * NSLOT + slot];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        la[jb][l][c] = M > 0 ? La[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+
+  // omega-weighted memory-variable adjoints per stress component, rows [c][b]
+  R* const Cx = reg + L::C;
+  if (M > 0) {
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+      const int b = q + LPE * jb;
+      if (b < B && act)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          R w = R(0);
+#pragma unroll
+          for (int l = 0; l < MM; ++l) w += om[l] * la[jb][l][c];
+          Cx[c * B + b] = w;
+        }
+    }
+  }
+  __syncthreads();
+  // face adjoints of this lane's rows: elastic row q, memory-variable row 9+q
+  R ue[4 * FP], ua[4 * FP];
+  RF::trace(le, ue);
+  {
+    R wrow[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) wrow[b] = (M > 0 && is_stress) ? Cx[q * B + b] : R(0);
+    RF::trace(wrow, ua);
+  }
+  __syncthreads();
+
+  // ================================================================ ADJ_UPDATE
+  if (a.kind == KIND_ADJ_UPDATE) {
+    if (!valid) return;
+    const int n = step_fin_of(a, cl);
+    R* const S1 = reinterpret_cast<R*>(ad.S1);
+    R* const S2 = reinterpret_cast<R*>(ad.S2);
+    R* const S3 = reinterpret_cast<R*>(ad.S3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int nb = FI[3 * i];
+      if (nb < 0) continue;
+      const int code = FI[3 * i + 1];
+      const size_t aux = (size_t)FI[3 * i + 2];
+      const int j = code & 15, rel = ((code >> 8) & 15) - 1;
+      const size_t fo = (size_t)j * ADJ_ROWS * FP;
+      R* d1 = nullptr;
+      R* d2 = nullptr;
+      R sgn2 = R(1);
+      if (rel == 0) {
+        d1 = S1 + (size_t)nb * sstride + fo;
+      } else if (rel < 0) {          // finer neighbour: its B3
+        d1 = S3 + aux * sstride + fo;
+      } else if ((n & 1) == 0) {     // coarser neighbour, first half: its B2
+        d1 = S2 + aux * sstride + fo;
+      } else {                       // coarser neighbour, second half: B1 - B2
+        d1 = S1 + (size_t)nb * sstride + fo;
+        d2 = S2 + aux * sstride + fo;
+        sgn2 = R(-1);
+      }
+#pragma unroll
+      for (int f = 0; f < FP; ++f) {
+        d1[q * FP + f] += ue[i * FP + f];
+        if (is_stress) d1[(9 + q) * FP + f] += ua[i * FP + f];
+      }
+      if (d2) {
+#pragma unroll
+        for (int f = 0; f < FP; ++f) {
+          d2[q * FP + f] += sgn2 * ue[i * FP + f];
+          if (is_stress) d2[(9 + q) * FP + f] += sgn2 * ua[i * FP + f];
+        }
+      }
+    }
+    return;
+  }
+
+  // ================================================================ ADJ_PREDICT
+  for (int w = lane; w < EPW * NG; w += 64) gsh[w] = 0.0;
+  const int nn = step_new_of(a, cl);
+  const int eflags = FI[12];
+  const bool has_b2 = (eflags & EF_HAS_FINER) != 0;
+  const bool has_b3 = (eflags & EF_HAS_COARSER) != 0;
+  const bool any_b2 = __any(has_b2);
+  const int rec_slot = FI[15];
+  R* const grad = reg + L::GRD;
+  R* const Xr = reg + L::X;
+  R* const Ur = reg + L::U;
+  R* const Pm = reg + L::PM;
+  R* const De = reinterpret_cast<R*>(ad.De);
+  R* const Da = reinterpret_cast<R*>(ad.Da);
+  const int eA = (6 + qi) * 3 * B + qj * B;   // d v_i / d x_j
+  const int eB = (6 + qj) * 3 * B + qi * B;   // d v_j / d x_i
+  const int d0 = 6 * 3 * B + 0 * B, d1 = 7 * 3 * B + 1 * B, d2 = 8 * 3 * B + 2 * B;
+  int rA = 0, rB = 0, rC = 0;
+  if (!is_stress) {
+    const int i = q - 6;
+    rA = sym_index(i, 0) * 3 * B + 0 * B;
+    rB = sym_index(i, 1) * 3 * B + 1 * B;
+    rC = sym_index(i, 2) * 3 * B + 2 * B;
+  }
+
+  // ---------------------------------------------- forward recompute: D_d, T, T2
+  R te[B], t2[B];
+  {
+    const R* Se = reinterpret_cast<const R*>(ad.Se);
+    const R* Sa = reinterpret_cast<const R*>(ad.Sa);
+    R de[B];
+    R dm[JB][MM][6];
+#pragma unroll
+    for (int b = 0; b < B; ++b) { de[b] = Se[(gbase + b) * NSLOT + slot]; te[b] = R(0); t2[b] = R(0); }
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+          dm[jb][l][c] = M > 0 ? Sa[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+#pragma unroll 1
+    for (int d = 0; d < O; ++d) {
+      const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
+      const bool more = d + 1 < O;
+#pragma unroll
+      for (int b = 0; b < B; ++b) { te[b] += c_d * de[b]; t2[b] += h_d * de[b]; }
+      if (valid) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) De[(((size_t)g * O + d) * B + b) * NSLOT + slot] = de[b];
+        if (M > 0)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int l = 0; l < MM; ++l)
+#pragma unroll
+              for (int c = 0; c < 6; ++c)
+                Da[(((((size_t)g * O + d) * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = dm[jb][l][c];
+      }
+      if (!more) break;
+      RF::ck_grad(de, G, grad + q * 3 * B);
+      __syncthreads();
+      if (M > 0) {
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+          const int b = q + LPE * jb;
+          if (b < B) {
+            R eps[6];
+            eps[0] = grad[6 * 3 * B + 0 * B + b];
+            eps[1] = grad[7 * 3 * B + 1 * B + b];
+            eps[2] = grad[8 * 3 * B + 2 * B + b];
+            eps[3] = R(0.5) * (grad[6 * 3 * B + 1 * B + b] + grad[7 * 3 * B + 0 * B + b]);
+            eps[4] = R(0.5) * (grad[7 * 3 * B + 2 * B + b] + grad[8 * 3 * B + 1 * B + b]);
+            eps[5] = R(0.5) * (grad[6 * 3 * B + 2 * B + b] + grad[8 * 3 * B + 0 * B + b]);
+            R cp[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int l = 0; l < MM; ++l) {
+              const R tr = dm[jb][l][0] + dm[jb][l][1] + dm[jb][l][2];
+#pragma unroll
+              for (int c = 0; c < 6; ++c) cp[c] -= bl[l] * dm[jb][l][c] + (c < 3 ? al[l] * tr : R(0));
+#pragma unroll
+              for (int c = 0; c < 6; ++c) dm[jb][l][c] = om[l] * (eps[c] - dm[jb][l][c]);
+            }
+            if (act)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) Cx[c * B + b] = cp[c];
+          }
+        }
+        __syncthreads();
+      }
+      if (is_stress) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const R cq = M > 0 ? Cx[q * B + b] : R(0);
+          const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+          const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+          de[b] = lam * delta * div + R(2) * mu * eps + cq;
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) de[b] = rho_inv * (grad[rA + b] + grad[rB + b] + grad[rC + b]);
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---------------------------------------------- A. volume kernel
+  R lte[B], lt2[B];     // adjoints of the element's time integrals (elastic rows)
+#pragma unroll
+  for (int b = 0; b < B; ++b) { lte[b] = R(0); lt2[b] = R(0); }
+  // material terms: V = -(lam delta div + 2 mu eps) (stress), -rho_inv div(sigma) (velocity)
+  RF::vol_grad(te, G, grad + q * 3 * B);
+  __syncthreads();
+  {
+    double s = 0.0;
+    if (is_stress) {
+      double sl = 0.0;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+        const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+        sl += (double)(le[b] * div);
+        s += (double)(le[b] * R(2) * eps);
+      }
+      if (valid) {
+        if (q < 3) gadd(gs, 1, -sl);
+        gadd(gs, 2, -s);
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < B; ++b) s += (double)(le[b] * (grad[rA + b] + grad[rB + b] + grad[rC + b]));
+      if (valid) gadd(gs, 0, -s);
+    }
+  }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int b = 0; b < B; ++b) Xr[q * B + b] = le[b];
+  __syncthreads();
+  {
+    // adjoint of the gradient entries of this row (the volume kernel reads
+    // the velocity gradients in the stress rows and memory variables, the
+    // stress gradients in the velocity rows)
+    R gb[3 * B];
+    if (!is_stress) {
+      const int i = q - 6;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int sk = sym_index(i, k);
+        const R fm = i == k ? R(2) : R(1), fa = i == k ? R(1) : R(0.5);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          R v = -fm * mu * Xr[sk * B + b] - (M > 0 ? fa * Cx[sk * B + b] : R(0));
+          if (i == k) v -= lam * (Xr[0 * B + b] + Xr[1 * B + b] + Xr[2 * B + b]);
+          gb[k * B + b] = v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        // entry (q, k) is read by velocity row i' with sym(i', k) == q
+        int iv = -1;
+        if (k == qj) iv = qi;
+        else if (k == qi) iv = qj;
+#pragma unroll
+        for (int b = 0; b < B; ++b) gb[k * B + b] = iv >= 0 ? -rho_inv * Xr[(6 + iv) * B + b] : R(0);
+      }
+    }
+    RF::vol_grad_T(gb, G, lte);
+  }
+  __syncthreads();
+
+  // ---------------------------------------------- B. own surface part
+  R pt[4 * FP];
+  RF::trace(te, pt);
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int f = 0; f < FP; ++f) {
+        Ur[(i * ADJ_ROWS + q) * FP + f] = ue[i * FP + f];
+        if (is_stress) Ur[(i * ADJ_ROWS + 9 + q) * FP + f] = ua[i * FP + f];
+        Pm[(i * LPE + q) * FP + f] = pt[i * FP + f];
+      }
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int rr = 0; rr < (4 * F + LPE - 1) / LPE; ++rr) {
+    const int t = q + LPE * rr;
+    if (t < 4 * F && act) {
+      const int i = t / F, f = t % F;
+      const int bc = (FI[3 * i + 1] >> 4) & 15;
+      const R* fp = P + 20 + 6 * i;
+      R u[15], qm[9], zero9[9], qmb[9], qpb[9], pb[7];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) u[k] = (M > 0 || k < 9) ? Ur[(i * ADJ_ROWS + k) * FP + f] : R(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) { qm[k] = Pm[(i * LPE + k) * FP + f]; zero9[k] = R(0); qmb[k] = R(0); qpb[k] = R(0); }
+#pragma unroll
+      for (int k = 0; k < 7; ++k) pb[k] = R(0);
+      const R zpp = bc == 0 ? fp[4] : zp, zsp = bc == 0 ? fp[5] : zs;
+      godunov_adj<R>(u, qm, zero9, fp[0], fp[1], fp[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fp[3], bc, qmb, qpb, pb);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Pm[(i * LPE + k) * FP + f] = qmb[k];
+      if (valid) {
+        gadd(gs, 0, pb[0]);
+        gadd(gs, 1, pb[1]);
+        gadd(gs, 2, pb[2]);
+        gadd(gs, 3, pb[3]);
+        gadd(gs, 4, pb[4]);
+        gadd(gs, bc == 0 ? 11 + 2 * i : 3, pb[5]);
+        gadd(gs, bc == 0 ? 12 + 2 * i : 4, pb[6]);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    R pf[4 * FP];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int f = 0; f < FP; ++f) pf[i * FP + f] = Pm[(i * LPE + q) * FP + f];
+    RF::lift(pf, lte);
+  }
+  __syncthreads();
+
+  // ---------------------------------------------- C, D. neighbour data read from this element's buffers
+  R* const S1 = reinterpret_cast<R*>(ad.S1);
+  R* const S2 = reinterpret_cast<R*>(ad.S2);
+  R* const S3 = reinterpret_cast<R*>(ad.S3);
+#pragma unroll 1
+  for (int phase = 0; phase < 2; ++phase) {
+    // phase 0: B1 (and B3, the same trace); phase 1: B2
+    if (phase == 1 && !any_b2) break;
+    if (phase == 1) RF::trace(t2, pt);
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool nbr = FI[3 * i] >= 0;
+        R* s1 = phase == 0 ? S1 + (size_t)elem * sstride + (size_t)i * ADJ_ROWS * FP
+                           : (has_b2 ? S2 + (size_t)FI[13] * sstride + (size_t)i * ADJ_ROWS * FP : nullptr);
+        R* s3 = (phase == 0 && has_b3) ? S3 + (size_t)FI[14] * sstride + (size_t)i * ADJ_ROWS * FP : nullptr;
+        const bool clear3 = (nn & 1) == 0;
+#pragma unroll
+        for (int f = 0; f < FP; ++f) {
+          R ve = R(0), va = R(0);
+          if (valid && nbr && s1) {
+            ve = s1[q * FP + f];
+            if (is_stress) va = s1[(9 + q) * FP + f];
+            s1[q * FP + f] = R(0);
+            if (is_stress) s1[(9 + q) * FP + f] = R(0);
+          }
+          if (valid && nbr && s3) {
+            ve += s3[q * FP + f];
+            if (is_stress) va += s3[(9 + q) * FP + f];
+            if (clear3) {
+              s3[q * FP + f] = R(0);
+              if (is_stress) s3[(9 + q) * FP + f] = R(0);
+            }
+          }
+          Ur[(i * ADJ_ROWS + q) * FP + f] = ve;
+          if (is_stress) Ur[(i * ADJ_ROWS + 9 + q) * FP + f] = va;
+          Pm[(i * LPE + q) * FP + f] = pt[i * FP + f];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int rr = 0; rr < (4 * F + LPE - 1) / LPE; ++rr) {
+      const int t = q + LPE * rr;
+      if (t < 4 * F && act) {
+        const int i = t / F, f = t % F;
+        const int nb = FI[3 * i];
+        R qpb[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) qpb[k] = R(0);
+        if (nb >= 0) {
+          // the flux of the neighbour across face i, seen from its face j
+          const int j = FI[3 * i + 1] & 15;
+          const R* Pn = reinterpret_cast<const R*>(p.P) + (size_t)nb * NPARAM;
+          const R* fn = Pn + 20 + 6 * j;
+          R u[15], qpv[9], zero9[9], qmb[9], pb[7];
+#pragma unroll
+          for (int k = 0; k < 15; ++k) u[k] = (M > 0 || k < 9) ? Ur[(i * ADJ_ROWS + k) * FP + f] : R(0);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) { qpv[k] = Pm[(i * LPE + k) * FP + f]; zero9[k] = R(0); qmb[k] = R(0); }
+#pragma unroll
+          for (int k = 0; k < 7; ++k) pb[k] = R(0);
+          godunov_adj<R>(u, zero9, qpv, fn[0], fn[1], fn[2], Pn[12], Pn[13], fn[4], fn[5], Pn[10], Pn[11], Pn[9],
+                         fn[3], 0, qmb, qpb, pb);
+          if (valid)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) gadd(gs, 19 + 7 * i + k, pb[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Pm[(i * LPE + k) * FP + f] = qpb[k];
+      }
+    }
+    __syncthreads();
+    {
+      R pf[4 * FP];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) pf[i * FP + f] = Pm[(i * LPE + q) * FP + f];
+      if (phase == 0) RF::lift(pf, lte);
+      else if (has_b2) RF::lift(pf, lt2);
+    }
+    __syncthreads();
+  }
+
+  // ---------------------------------------------- E. time kernel backwards
+  R nbe[B];                 // adjoint of D_{d+1} (elastic row)
+  R nbm[JB][MM][6];         // adjoint of D_{d+1} (memory variables)
+#pragma unroll
+  for (int b = 0; b < B; ++b) nbe[b] = R(0);
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nbm[jb][l][c] = R(0);
+  R* const recDb = reinterpret_cast<R*>(ad.recDb);
+#pragma unroll 1
+  for (int d = O - 1; d >= 0; --d) {
+    const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
+    const bool more = d + 1 < O;
+    R de[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) de[b] = De[(((size_t)g * O + d) * B + b) * NSLOT + slot];
+    R cur[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) cur[b] = c_d * lte[b] + h_d * lt2[b];
+    if (rec_slot >= 0 && valid) {
+      R* rd = recDb + (((size_t)rec_slot * O + d) * LPE + q) * B;
+#pragma unroll
+      for (int b = 0; b < B; ++b) { cur[b] += rd[b]; rd[b] = R(0); }
+    }
+    if (more) {
+      // D_{d+1} = L(D_d): material terms with the forward gradients of D_d
+      RF::ck_grad(de, G, grad + q * 3 * B);
+      __syncthreads();
+      {
+        double s = 0.0;
+        if (is_stress) {
+          double sl = 0.0;
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            const R eps = R(0.5) * (grad[eA + b] + grad[eB + b]);
+            const R div = grad[d0 + b] + grad[d1 + b] + grad[d2 + b];
+            sl += (double)(nbe[b] * div);
+            s += (double)(nbe[b] * R(2) * eps);
+          }
+          if (valid) {
+            if (q < 3) gadd(gs, 1, sl);
+            gadd(gs, 2, s);
+          }
+        } else {
+#pragma unroll
+          for (int b = 0; b < B; ++b) s += (double)(nbe[b] * (grad[rA + b] + grad[rB + b] + grad[rC + b]));
+          if (valid) gadd(gs, 0, s);
+        }
+      }
+      __syncthreads();
+      // adjoint of the gradient entries read by D_{d+1}
+      if (act)
+#pragma unroll
+        for (int b = 0; b < B; ++b) Xr[q * B + b] = nbe[b];
+      if (M > 0) {
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+          const int b = q + LPE * jb;
+          if (b < B && act)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              R w = R(0);
+#pragma unroll
+              for (int l = 0; l < MM; ++l) w += om[l] * nbm[jb][l][c];
+              Cx[c * B + b] = w;
+            }
+        }
+      }
+      __syncthreads();
+      R gb[3 * B];
+      if (!is_stress) {
+        const int i = q - 6;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int sk = sym_index(i, k);
+          const R fm = i == k ? R(2) : R(1), fa = i == k ? R(1) : R(0.5);
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            R v = fm * mu * Xr[sk * B + b] + (M > 0 ? fa * Cx[sk * B + b] : R(0));
+            if (i == k) v += lam * (Xr[0 * B + b] + Xr[1 * B + b] + Xr[2 * B + b]);
+            gb[k * B + b] = v;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          int iv = -1;
+          if (k == qj) iv = qi;
+          else if (k == qi) iv = qj;
+#pragma unroll
+          for (int b = 0; b < B; ++b) gb[k * B + b] = iv >= 0 ? rho_inv * Xr[(6 + iv) * B + b] : R(0);
+        }
+      }
+      RF::ck_grad_T(gb, G, cur);
+      __syncthreads();
+    }
+    if (M > 0) {
+      // coupling E (memory variables -> stresses): cq_d enters the volume
+      // term c_d cq_d and the next derivative
+      if (is_stress && act)
+#pragma unroll
+        for (int b = 0; b < B; ++b) Xr[q * B + b] = c_d * le[b] + (more ? nbe[b] : R(0));
+      __syncthreads();
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int b = q + LPE * jb;
+        if (b < B) {
+          R cqb[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) cqb[c] = Xr[c * B + b];
+          const R cqt = cqb[0] + cqb[1] + cqb[2];
+#pragma unroll
+          for (int l = 0; l < MM; ++l) {
+            R dmd[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+              dmd[c] = Da[(((((size_t)g * O + d) * JB + jb) * MM + l) * 6 + c) * NSLOT + slot];
+            const R tr = dmd[0] + dmd[1] + dmd[2];
+            double ga = 0.0, gbb = 0.0;
+            ga -= (double)(cqt * tr);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) gbb -= (double)(cqb[c] * dmd[c]);
+            if (valid) {
+              gadd(gs, 5 + 2 * l, ga);
+              gadd(gs, 6 + 2 * l, gbb);
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              // -omega_l c_d T^a volume term, -omega_l theta in the next
+              // derivative, coupling into the stresses
+              R v = -om[l] * c_d * la[jb][l][c] - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
+              if (more) v -= om[l] * nbm[jb][l][c];
+              nbm[jb][l][c] = v;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) nbe[b] = cur[b];
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) le[b] += nbe[b];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) la[jb][l][c] += nbm[jb][l][c];
+  if (valid) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) Le[(gbase + b) * NSLOT + slot] = le[b];
+    if (M > 0)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) La[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = la[jb][l][c];
+  }
+  __syncthreads();
+  if (valid)
+    for (int w = q; w < NG; w += LPE) ad.gacc[(size_t)elem * NG + w] += gsh[ec * NG + w];
+}
+
+// adjoint of the receiver samples: the derivatives of the receiver slots get
+// sum_s (t_s - t^n)^d / d! * seisbar_s phi(x_r) for the samples in the step
+// that starts at this level
+template <class R, int O, int M>
+__global__ void k_receivers_adj(KPtrs p, APtrs ad, LevelArgs a, RecArgs r, const double* seis_b) {
+  constexpr int B = edg_gen::Ref<O>::B;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rec = t / LPE, q = t % LPE;
+  if (rec >= r.n) return;
+  const int elem = r.elem[rec];
+  if (elem >= a.end) return;
+  const int cl = cluster_of(a, elem);
+  const double dt = a.dt[cl];
+  const int n = step_new_of(a, cl);
+  const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
+  double vb[O];
+  for (int d = 0; d < O; ++d) vb[d] = 0.0;
+  long long s = (long long)floor(t0 / r.dt_sample) - 1;
+  if (s < 0) s = 0;
+  bool any = false;
+  for (; s < r.ns && (double)s * r.dt_sample < t1; ++s) {
+    const double ts = (double)s * r.dt_sample;
+    if (ts < t0) continue;
+    const double x = ts - t0, sb = seis_b[((size_t)rec * r.ns + s) * LPE + q];
+    double pw = 1.0, fact = 1.0;
+    for (int d = 0; d < O; ++d) {
+      vb[d] += pw / fact * sb;
+      pw *= x;
+      fact *= (double)(d + 1);
+    }
+    any = true;
+  }
+  if (!any) return;
+  R* D = reinterpret_cast<R*>(ad.recDb) + (size_t)r.slot[rec] * O * LPE * B;
+  for (int d = 0; d < O; ++d)
+    for (int b = 0; b < B; ++b) atomicAdd(&D[((size_t)d * LPE + q) * B + b], R(vb[d] * r.phi[(size_t)rec * B + b]));
+}
+
+}  // namespace
+
+template <class R, int O, int M>
+int launch_adjoint(const KPtrs& p, const APtrs& ad, const LevelArgs& a, hipStream_t st) {
+  const int groups = (a.end + EPW - 1) / EPW;
+  if (groups <= 0) return 0;
+  hipLaunchKernelGGL((k_adjoint<R, O, M>), dim3(groups), dim3(64), 0, st, p, ad, a);
+  return (int)hipGetLastError();
+}
+
+template <class R, int O, int M>
+int launch_receivers_adj(const KPtrs& p, const APtrs& ad, const LevelArgs& a, const RecArgs& r, const double* seis_b,
+                         hipStream_t st) {
+  if (r.n <= 0) return 0;
+  const int total = r.n * LPE;
+  hipLaunchKernelGGL((k_receivers_adj<R, O, M>), dim3((total + 127) / 128), dim3(128), 0, st, p, ad, a, r, seis_b);
+  return (int)hipGetLastError();
+}
+
+#define EDG_ADJ_INST(R, O, M)                                                                    \
+  template int launch_adjoint<R, O, M>(const KPtrs&, const APtrs&, const LevelArgs&, hipStream_t); \
+  template int launch_receivers_adj<R, O, M>(const KPtrs&, const APtrs&, const LevelArgs&, const RecArgs&, \
+                                             const double*, hipStream_t);
+
+EDG_FOR_EACH_VARIANT(EDG_ADJ_INST)
+
+}  // namespace edg
+
+// Host evaluation of the face flux and its reverse mode (FP64), for CPU
+// checks of the adjoint's flux transpose.  prm = (nx, ny, nz, zpm, zsm, zpp,
+// zsp, lam, mu, rho_inv, s); out [15]; qm_b, qp_b [9] and pb [7] are
+// overwritten with the adjoint of the outputs u [15].
+extern "C" int edg_godunov_host(int32_t bc, const double* qm, const double* qp, const double* prm, const double* u,
+                                double* out, double* qm_b, double* qp_b, double* pb) {
+  if (!qm || !qp || !prm || !u || !out || !qm_b || !qp_b || !pb || bc < 0 || bc > 2) return -1;
+  edg::godunov<double>(qm, qp, prm[0], prm[1], prm[2], prm[3], prm[4], prm[5], prm[6], prm[7], prm[8], prm[9],
+                       prm[10], bc, out);
+  for (int k = 0; k < 9; ++k) qm_b[k] = qp_b[k] = 0.0;
+  for (int k = 0; k < 7; ++k) pb[k] = 0.0;
+  edg::godunov_adj<double>(u, qm, qp, prm[0], prm[1], prm[2], prm[3], prm[4], prm[5], prm[6], prm[7], prm[8], prm[9],
+                           prm[10], bc, qm_b, qp_b, pb);
+  return 0;
+}

@@ -1,0 +1,291 @@
+// Device helpers shared by the forward and adjoint kernels (internal):
+// the lane mapping constants, the level clock, the workgroup -> (element
+// group, run) map and the Godunov flux of one face mode.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace edg {
+
+namespace {
+
+constexpr int EPW = 7;   // elements per wave
+constexpr int LPE = 9;   // lanes per element
+constexpr int NSLOT = EPW * LPE;  // 63 elastic slots per mode in the tiled layout
+
+__device__ __forceinline__ int sym_index(int i, int j) {
+  // (0,0)->0 (1,1)->1 (2,2)->2 (0,1)->3 (1,2)->4 (0,2)->5
+  if (i == j) return i;
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  return a == 0 ? (b == 1 ? 3 : 5) : 4;
+}
+
+__device__ __forceinline__ int cluster_of(const LevelArgs& a, int elem) {
+  int c = 0;
+#pragma unroll
+  for (int l = 0; l < MAX_CLUSTERS - 1; ++l)
+    if (l < a.n_clusters - 1 && elem >= a.cl_end[l]) c = l + 1;
+  return c;
+}
+
+// Godunov flux of one face mode: qm / qp are the 9 elastic trace coefficients
+// of this element and of the outside state; writes s * (A_n q*) for the 9
+// elastic rows and s * (strain-rate flux) for the 6 memory-variable rows
+// (unscaled by omega), where s = 2|S_i| / |det J| (the surface kernel's
+// -(1/|det J|) int_face phi ... with the sign folded in).
+template <class R>
+__host__ __device__ __forceinline__ void godunov(const R* qm, const R* qp, R nx, R ny, R nz, R zpm, R zsm, R zpp, R zsp,
+                                        R lam, R mu, R rho_inv, R s, int bc, R* out) {
+  // tractions sigma n and velocities
+  const R tmx = qm[0] * nx + qm[3] * ny + qm[5] * nz;
+  const R tmy = qm[3] * nx + qm[1] * ny + qm[4] * nz;
+  const R tmz = qm[5] * nx + qm[4] * ny + qm[2] * nz;
+  const R vmx = qm[6], vmy = qm[7], vmz = qm[8];
+  R tpx, tpy, tpz, vpx, vpy, vpz;
+  if (bc == 0) {
+    tpx = qp[0] * nx + qp[3] * ny + qp[5] * nz;
+    tpy = qp[3] * nx + qp[1] * ny + qp[4] * nz;
+    tpz = qp[5] * nx + qp[4] * ny + qp[2] * nz;
+    vpx = qp[6]; vpy = qp[7]; vpz = qp[8];
+  } else if (bc == 1) {  // free surface: mirror state (traction flips, velocity kept)
+    tpx = -tmx; tpy = -tmy; tpz = -tmz;
+    vpx = vmx; vpy = vmy; vpz = vmz;
+  } else {               // absorbing: zero outside state
+    tpx = tpy = tpz = R(0);
+    vpx = vpy = vpz = R(0);
+  }
+  const R tnm = tmx * nx + tmy * ny + tmz * nz, vnm = vmx * nx + vmy * ny + vmz * nz;
+  const R tnp = tpx * nx + tpy * ny + tpz * nz, vnp = vpx * nx + vpy * ny + vpz * nz;
+  const R ip = R(1) / (zpm + zpp), is = R(1) / (zsm + zsp);
+  const R vn = (zpm * vnm + zpp * vnp + tnp - tnm) * ip;
+  const R tn = (zpp * tnm + zpm * tnp + zpm * zpp * (vnp - vnm)) * ip;
+  // tangential parts
+  const R tTmx = tmx - tnm * nx, tTmy = tmy - tnm * ny, tTmz = tmz - tnm * nz;
+  const R vTmx = vmx - vnm * nx, vTmy = vmy - vnm * ny, vTmz = vmz - vnm * nz;
+  const R tTpx = tpx - tnp * nx, tTpy = tpy - tnp * ny, tTpz = tpz - tnp * nz;
+  const R vTpx = vpx - vnp * nx, vTpy = vpy - vnp * ny, vTpz = vpz - vnp * nz;
+  const R zz = zsm * zsp;
+  const R vx = vn * nx + (zsm * vTmx + zsp * vTpx + tTpx - tTmx) * is;
+  const R vy = vn * ny + (zsm * vTmy + zsp * vTpy + tTpy - tTmy) * is;
+  const R vz = vn * nz + (zsm * vTmz + zsp * vTpz + tTpz - tTmz) * is;
+  const R tx = tn * nx + (zsp * tTmx + zsm * tTpx + zz * (vTpx - vTmx)) * is;
+  const R ty = tn * ny + (zsp * tTmy + zsm * tTpy + zz * (vTpy - vTmy)) * is;
+  const R tz = tn * nz + (zsp * tTmz + zsm * tTpz + zz * (vTpz - vTmz)) * is;
+  // flux A_n q*: stresses -(lam (v.n) I + mu (n v^T + v n^T)), velocities -t/rho;
+  // multiplied by -s for the surface term: +s (...)
+  const R lvn = lam * vn;
+  const R ms = mu * s;
+  out[0] = s * lvn + R(2) * ms * nx * vx;
+  out[1] = s * lvn + R(2) * ms * ny * vy;
+  out[2] = s * lvn + R(2) * ms * nz * vz;
+  out[3] = ms * (nx * vy + ny * vx);
+  out[4] = ms * (ny * vz + nz * vy);
+  out[5] = ms * (nx * vz + nz * vx);
+  const R sr = s * rho_inv;
+  out[6] = sr * tx;
+  out[7] = sr * ty;
+  out[8] = sr * tz;
+  // memory-variable rows: -(1/2)(n v^T + v n^T), times -s
+  const R hs = R(0.5) * s;
+  out[9] = s * nx * vx;
+  out[10] = s * ny * vy;
+  out[11] = s * nz * vz;
+  out[12] = hs * (nx * vy + ny * vx);
+  out[13] = hs * (ny * vz + nz * vy);
+  out[14] = hs * (nx * vz + nz * vx);
+}
+
+// Reverse mode of godunov(): for the adjoint u of its 15 outputs, adds
+// (d out / d qm)^T u to qm_b, (d out / d qp)^T u to qp_b (interior faces) and
+// the derivatives of <u, out> in (rho_inv, lam, mu, zpm, zsm, zpp, zsp) to
+// pb[0..6].  out is linear in (qm, qp), so the parameter derivatives are
+// bilinear: they use the states passed in (zeros for a side that another
+// element accounts for).
+template <class R>
+__host__ __device__ __forceinline__ void godunov_adj(const R* u, const R* qm, const R* qp, R nx, R ny, R nz, R zpm,
+                                                     R zsm, R zpp, R zsp, R lam, R mu, R rho_inv, R s, int bc,
+                                                     R* qm_b, R* qp_b, R* pb) {
+  const R n[3] = {nx, ny, nz};
+  // forward intermediates
+  R tm[3], vm[3], tp[3], vp[3];
+  tm[0] = qm[0] * nx + qm[3] * ny + qm[5] * nz;
+  tm[1] = qm[3] * nx + qm[1] * ny + qm[4] * nz;
+  tm[2] = qm[5] * nx + qm[4] * ny + qm[2] * nz;
+  vm[0] = qm[6]; vm[1] = qm[7]; vm[2] = qm[8];
+  if (bc == 0) {
+    tp[0] = qp[0] * nx + qp[3] * ny + qp[5] * nz;
+    tp[1] = qp[3] * nx + qp[1] * ny + qp[4] * nz;
+    tp[2] = qp[5] * nx + qp[4] * ny + qp[2] * nz;
+    vp[0] = qp[6]; vp[1] = qp[7]; vp[2] = qp[8];
+  } else if (bc == 1) {
+    for (int c = 0; c < 3; ++c) { tp[c] = -tm[c]; vp[c] = vm[c]; }
+  } else {
+    for (int c = 0; c < 3; ++c) { tp[c] = R(0); vp[c] = R(0); }
+  }
+  const R tnm = tm[0] * nx + tm[1] * ny + tm[2] * nz, vnm = vm[0] * nx + vm[1] * ny + vm[2] * nz;
+  const R tnp = tp[0] * nx + tp[1] * ny + tp[2] * nz, vnp = vp[0] * nx + vp[1] * ny + vp[2] * nz;
+  const R ip = R(1) / (zpm + zpp), is = R(1) / (zsm + zsp);
+  const R Y = zpm * vnm + zpp * vnp + tnp - tnm;
+  const R Z = zpp * tnm + zpm * tnp + zpm * zpp * (vnp - vnm);
+  const R vn = Y * ip, tn = Z * ip;
+  const R zz = zsm * zsp;
+  R tTm[3], vTm[3], tTp[3], vTp[3], W[3], X[3], v[3], t[3];
+  for (int c = 0; c < 3; ++c) {
+    tTm[c] = tm[c] - tnm * n[c];
+    vTm[c] = vm[c] - vnm * n[c];
+    tTp[c] = tp[c] - tnp * n[c];
+    vTp[c] = vp[c] - vnp * n[c];
+    W[c] = zsm * vTm[c] + zsp * vTp[c] + tTp[c] - tTm[c];
+    X[c] = zsp * tTm[c] + zsm * tTp[c] + zz * (vTp[c] - vTm[c]);
+    v[c] = vn * n[c] + W[c] * is;
+    t[c] = tn * n[c] + X[c] * is;
+  }
+  // outputs -> v, t, material parameters
+  R vb[3] = {R(0), R(0), R(0)}, tb[3] = {R(0), R(0), R(0)};
+  R vnb = R(0), lamb = R(0), mub = R(0), rib = R(0);
+  const R hs = R(0.5) * s;
+  for (int c = 0; c < 3; ++c) {
+    vnb += s * lam * u[c];
+    lamb += s * vn * u[c];
+    vb[c] += R(2) * mu * s * n[c] * u[c];
+    mub += R(2) * s * n[c] * v[c] * u[c];
+    tb[c] += s * rho_inv * u[6 + c];
+    rib += s * t[c] * u[6 + c];
+    vb[c] += s * n[c] * u[9 + c];
+  }
+  const int pa[3] = {0, 1, 0}, pc[3] = {1, 2, 2};   // (x,y), (y,z), (x,z)
+  for (int k = 0; k < 3; ++k) {
+    const int a = pa[k], b = pc[k];
+    const R ue = u[3 + k], ua = u[12 + k];
+    vb[b] += mu * s * n[a] * ue + hs * n[a] * ua;
+    vb[a] += mu * s * n[b] * ue + hs * n[b] * ua;
+    mub += s * (n[a] * v[b] + n[b] * v[a]) * ue;
+  }
+  // v = vn n + W is, t = tn n + X is
+  R Wb[3], Xb[3];
+  R isb = R(0), tnb = R(0);
+  for (int c = 0; c < 3; ++c) {
+    vnb += vb[c] * n[c];
+    tnb += tb[c] * n[c];
+    Wb[c] = vb[c] * is;
+    Xb[c] = tb[c] * is;
+    isb += vb[c] * W[c] + tb[c] * X[c];
+  }
+  R vTmb[3], vTpb[3], tTmb[3], tTpb[3];
+  R zsmb = R(0), zspb = R(0), zzb = R(0);
+  for (int c = 0; c < 3; ++c) {
+    vTmb[c] = zsm * Wb[c] - zz * Xb[c];
+    vTpb[c] = zsp * Wb[c] + zz * Xb[c];
+    tTpb[c] = Wb[c] + zsm * Xb[c];
+    tTmb[c] = -Wb[c] + zsp * Xb[c];
+    zsmb += Wb[c] * vTm[c] + Xb[c] * tTp[c];
+    zspb += Wb[c] * vTp[c] + Xb[c] * tTm[c];
+    zzb += Xb[c] * (vTp[c] - vTm[c]);
+  }
+  zsmb += zsp * zzb;
+  zspb += zsm * zzb;
+  // tangential parts
+  R tmb[3], vmb[3], tpb[3], vpb[3];
+  R tnmb = R(0), vnmb = R(0), tnpb = R(0), vnpb = R(0);
+  for (int c = 0; c < 3; ++c) {
+    tmb[c] = tTmb[c];
+    vmb[c] = vTmb[c];
+    tpb[c] = tTpb[c];
+    vpb[c] = vTpb[c];
+    tnmb -= tTmb[c] * n[c];
+    vnmb -= vTmb[c] * n[c];
+    tnpb -= tTpb[c] * n[c];
+    vnpb -= vTpb[c] * n[c];
+  }
+  // normal parts
+  const R Yb = vnb * ip, Zb = tnb * ip;
+  const R ipb = vnb * Y + tnb * Z;
+  vnmb += zpm * Yb - zpm * zpp * Zb;
+  vnpb += zpp * Yb + zpm * zpp * Zb;
+  tnpb += Yb + zpm * Zb;
+  tnmb += -Yb + zpp * Zb;
+  R zpmb = Yb * vnm + Zb * (tnp + zpp * (vnp - vnm));
+  R zppb = Yb * vnp + Zb * (tnm + zpm * (vnp - vnm));
+  zpmb -= ipb * ip * ip;
+  zppb -= ipb * ip * ip;
+  zsmb -= isb * is * is;
+  zspb -= isb * is * is;
+  for (int c = 0; c < 3; ++c) {
+    tmb[c] += tnmb * n[c];
+    vmb[c] += vnmb * n[c];
+    tpb[c] += tnpb * n[c];
+    vpb[c] += vnpb * n[c];
+  }
+  // outside state
+  if (bc == 0) {
+    qp_b[0] += tpb[0] * nx;
+    qp_b[1] += tpb[1] * ny;
+    qp_b[2] += tpb[2] * nz;
+    qp_b[3] += tpb[0] * ny + tpb[1] * nx;
+    qp_b[4] += tpb[1] * nz + tpb[2] * ny;
+    qp_b[5] += tpb[0] * nz + tpb[2] * nx;
+    qp_b[6] += vpb[0];
+    qp_b[7] += vpb[1];
+    qp_b[8] += vpb[2];
+  } else if (bc == 1) {
+    for (int c = 0; c < 3; ++c) {
+      tmb[c] -= tpb[c];
+      vmb[c] += vpb[c];
+    }
+  }
+  qm_b[0] += tmb[0] * nx;
+  qm_b[1] += tmb[1] * ny;
+  qm_b[2] += tmb[2] * nz;
+  qm_b[3] += tmb[0] * ny + tmb[1] * nx;
+  qm_b[4] += tmb[1] * nz + tmb[2] * ny;
+  qm_b[5] += tmb[0] * nz + tmb[2] * nx;
+  qm_b[6] += vmb[0];
+  qm_b[7] += vmb[1];
+  qm_b[8] += vmb[2];
+  pb[0] += rib;
+  pb[1] += lamb;
+  pb[2] += mub;
+  pb[3] += zpmb;
+  pb[4] += zsmb;
+  pb[5] += zppb;
+  pb[6] += zspb;
+}
+
+// Steps of cluster cl at the processed level (see LevelArgs::clock).
+__device__ __forceinline__ int step_new_of(const LevelArgs& a, int cl) {
+  return (int)((*a.clock + a.jrel) >> cl);
+}
+__device__ __forceinline__ int step_fin_of(const LevelArgs& a, int cl) { return step_new_of(a, cl) - 1; }
+
+// Linear workgroup id -> (element group, run).  Workgroups are dealt to the
+// 8 XCDs round robin; with xcd_remap the ids of one XCD cover a contiguous
+// range of the (run-major) group space, so neighbouring elements share that
+// XCD's L2.  A bijection for any grid size.
+__device__ __forceinline__ void group_and_run(const LevelArgs& a, int& g, int& run) {
+  const int nx = gridDim.x;
+  int lin = blockIdx.x + blockIdx.y * nx;
+  if (a.xcd_remap) {
+    const int total = nx * gridDim.y;
+    const int q = total / 8, r = total % 8;
+    const int x = lin % 8, k = lin / 8;
+    lin = x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+  }
+  g = lin % nx;
+  run = a.run0 + lin / nx;
+}
+
+// State arrays are stacked run after run: the pointers of one run.
+template <class R>
+__device__ __forceinline__ void select_run(KPtrs& p, int run) {
+  p.Qe = reinterpret_cast<R*>(p.Qe) + (size_t)run * p.run_qe;
+  p.Qa = reinterpret_cast<R*>(p.Qa) + (size_t)run * p.run_qa;
+  p.T1 = reinterpret_cast<R*>(p.T1) + (size_t)run * p.run_t1;
+  p.T2 = reinterpret_cast<R*>(p.T2) + (size_t)run * p.run_t2;
+  p.T3 = reinterpret_cast<R*>(p.T3) + (size_t)run * p.run_t3;
+  p.recD = reinterpret_cast<R*>(p.recD) + (size_t)run * p.run_recd;
+}
+
+}  // namespace
+
+}  // namespace edg

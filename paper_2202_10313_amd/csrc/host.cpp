@@ -100,6 +100,13 @@ struct edg_ctx {
   hipGraphExec_t cycle_exec = nullptr;
   hipGraph_t cycle_graph = nullptr;
 
+  // checkpoints of the forward state (adjoint): every ckpt_every cycles an
+  // advance starts a segment and stores the state at its start
+  int ckpt_every = 0;
+  std::vector<std::pair<int64_t, DevBuf>> ckpts;    // (level, Qe then Qa of run 0)
+  // adjoint buffers
+  DevBuf aLe, aLa, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal;
+
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
@@ -128,6 +135,11 @@ void dev_free(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
+}
+
+void drop_checkpoints(edg_ctx* c) {
+  for (auto& ck : c->ckpts) dev_free(ck.second);
+  c->ckpts.clear();
 }
 
 int dev_alloc(edg_ctx* c, DevBuf& b, size_t bytes) {
@@ -345,8 +357,11 @@ inline size_t qa_size(const edg_ctx* c) {
   return c->M > 0 ? (size_t)c->G * jb_count(c) * c->M * 6 * EPW * LPE : 1;
 }
 
+// caller-order DOFs [K][NQ][B] -> the tiled layout at dqe / dqa (device);
+// the vertex-sorting basis changes are orthogonal, so adjoints convert the
+// same way
 template <class R>
-int set_dofs_t(edg_ctx* c, int run, const double* dofs) {
+int set_dofs_to(edg_ctx* c, void* dqe, void* dqa, const double* dofs) {
   const int B = c->B, NQ = c->NQ;
   std::vector<R> he((size_t)c->G * B * EPW * LPE, R(0));
   std::vector<R> ha(qa_size(c), R(0));
@@ -370,20 +385,23 @@ int set_dofs_t(edg_ctx* c, int run, const double* dofs) {
       }
     }
   }
-  HIPCHK(c, hipMemcpy((R*)c->Qe.p + run * c->run_qe, he.data(), he.size() * sizeof(R), hipMemcpyHostToDevice));
-  if (c->M > 0)
-    HIPCHK(c, hipMemcpy((R*)c->Qa.p + run * c->run_qa, ha.data(), ha.size() * sizeof(R), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(dqe, he.data(), he.size() * sizeof(R), hipMemcpyHostToDevice));
+  if (c->M > 0) HIPCHK(c, hipMemcpy(dqa, ha.data(), ha.size() * sizeof(R), hipMemcpyHostToDevice));
   return 0;
 }
 
 template <class R>
-int get_dofs_t(edg_ctx* c, int run, double* out) {
+int set_dofs_t(edg_ctx* c, int run, const double* dofs) {
+  return set_dofs_to<R>(c, (R*)c->Qe.p + run * c->run_qe, (R*)c->Qa.p + run * c->run_qa, dofs);
+}
+
+template <class R>
+int get_dofs_from(edg_ctx* c, const void* dqe, const void* dqa, double* out) {
   const int B = c->B, NQ = c->NQ;
   std::vector<R> he((size_t)c->G * B * EPW * LPE);
   std::vector<R> ha(qa_size(c));
-  HIPCHK(c, hipMemcpy(he.data(), (R*)c->Qe.p + run * c->run_qe, he.size() * sizeof(R), hipMemcpyDeviceToHost));
-  if (c->M > 0)
-    HIPCHK(c, hipMemcpy(ha.data(), (R*)c->Qa.p + run * c->run_qa, ha.size() * sizeof(R), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(he.data(), dqe, he.size() * sizeof(R), hipMemcpyDeviceToHost));
+  if (c->M > 0) HIPCHK(c, hipMemcpy(ha.data(), dqa, ha.size() * sizeof(R), hipMemcpyDeviceToHost));
   std::vector<double> row(B);
   for (int64_t k = 0; k < c->K; ++k) {
     const int64_t ki = c->user_to_internal[k];
@@ -407,6 +425,11 @@ int get_dofs_t(edg_ctx* c, int run, double* out) {
     }
   }
   return 0;
+}
+
+template <class R>
+int get_dofs_t(edg_ctx* c, int run, double* out) {
+  return get_dofs_from<R>(c, (R*)c->Qe.p + run * c->run_qe, (R*)c->Qa.p + run * c->run_qa, out);
 }
 
 // DOFs of selected elements: only the 7-element groups that hold them are
@@ -680,8 +703,10 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
 
 edg_ctx::~edg_ctx() {
   for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
-                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock})
+                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock, &aLe, &aLa, &aS1, &aS2, &aS3, &aDe, &aDa,
+                    &agacc, &arecDb, &aseis, &ahist, &afinal})
     dev_free(*b);
+  for (auto& ck : ckpts) dev_free(ck.second);
   for (auto& e : ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -847,6 +872,7 @@ int edg_upload_materials(edg_ctx* c, const double* rho, const double* vp, const 
     c->omega.clear();
   }
   c->have_mat = true;
+  drop_checkpoints(c);
   if (c->have_clusters) {  // re-derive operators, keep clusters and state
     if (c->cfg.fp64) {
       std::vector<double> P;
@@ -867,6 +893,7 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   if (!c) return EDG_EINVAL;
   if (!c->have_mesh || !c->have_mat) return fail(c, EDG_ESTATE, "upload mesh and materials first");
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  drop_checkpoints(c);
   const int64_t K = c->K;
   const int Nc = c->cfg.n_clusters, O = c->O;
   std::vector<double> dt(K);
@@ -975,6 +1002,7 @@ int edg_set_initial(edg_ctx* c, int32_t run, const double* dofs) {
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
   if (run < 0 || run >= c->runs || !dofs) return fail(c, EDG_EINVAL, "bad run or null dofs");
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  drop_checkpoints(c);
   return c->cfg.fp64 ? set_dofs_t<double>(c, run, dofs) : set_dofs_t<float>(c, run, dofs);
 }
 
@@ -995,6 +1023,7 @@ int edg_set_dofs_subset(edg_ctx* c, int32_t run, int64_t n, const int64_t* ids, 
     if (ids[i] < 0 || ids[i] >= c->K) return fail(c, EDG_EINVAL, "element index out of range");
   if (n == 0) return EDG_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  drop_checkpoints(c);
   return c->cfg.fp64 ? subset_dofs_t<double>(c, run, n, ids, dofs, nullptr)
                      : subset_dofs_t<float>(c, run, n, ids, dofs, nullptr);
 }
@@ -1020,6 +1049,7 @@ int edg_set_sources(edg_ctx* c, int32_t run, int64_t n, const double* xyz, const
     return fail(c, EDG_EINVAL, "bad source arguments");
   if (kind != EDG_STF_RICKER && kind != EDG_STF_HANN) return fail(c, EDG_EINVAL, "unknown source time function");
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  drop_checkpoints(c);
   std::vector<edg_ctx::Source> list;
   for (int64_t s = 0; s < n; ++s) {
     double xi[3];
@@ -1204,19 +1234,12 @@ int capture_cycle(edg_ctx* c, const AdvanceArgs& A) {
 
 }  // namespace
 
-int edg_advance_to(edg_ctx* c, double t) {
-  if (!c) return EDG_EINVAL;
-  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
-  HIPCHK(c, hipSetDevice(c->cfg.device));
+namespace {
+
+// nc >= 1 LTS cycles from the current synchronisation point: predict every
+// element, then the cycles (the last one only finishes its steps)
+int advance_cycles(edg_ctx* c, int64_t nc) {
   const int Nc = c->cfg.n_clusters;
-  const double sync = c->dt_cl[Nc - 1];
-  const double t_now = (double)c->level * c->dt_cl[0];
-  const double cycles = (t - t_now) / sync;
-  const double ncd = std::nearbyint(cycles);
-  if (ncd < 0 || std::fabs(cycles - ncd) > 1e-9 * std::max(1.0, std::fabs(cycles)))
-    return fail(c, EDG_ENOTSYNC, "time is not a synchronisation point after the current time");
-  if (ncd == 0) return EDG_OK;
-  const int64_t nc = (int64_t)ncd;
   const int64_t per = (int64_t)1 << (Nc - 1);
   const AdvanceArgs A = advance_args(c);
   const bool graph = (c->cfg.flags & EDG_FLAG_GRAPH) != 0;
@@ -1255,6 +1278,50 @@ int edg_advance_to(edg_ctx* c, double t) {
       c->t_launches += c->ev_launches[i];
       c->t_updates += c->ev_updates[i];
     }
+  }
+  return EDG_OK;
+}
+
+// stores the current state (run 0) as a checkpoint at the current level
+int store_checkpoint(edg_ctx* c) {
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  const size_t we = c->run_qe, wa = c->run_qa;
+  c->ckpts.emplace_back(c->level, DevBuf{});
+  int rc = dev_alloc(c, c->ckpts.back().second, (we + wa) * rs);
+  if (rc) {
+    c->ckpts.pop_back();
+    return rc;
+  }
+  char* dst = (char*)c->ckpts.back().second.p;
+  HIPCHK(c, hipMemcpyAsync(dst, c->Qe.p, we * rs, hipMemcpyDeviceToDevice, c->stream));
+  if (wa) HIPCHK(c, hipMemcpyAsync(dst + we * rs, c->Qa.p, wa * rs, hipMemcpyDeviceToDevice, c->stream));
+  return 0;
+}
+
+}  // namespace
+
+int edg_advance_to(edg_ctx* c, double t) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const int Nc = c->cfg.n_clusters;
+  const double sync = c->dt_cl[Nc - 1];
+  const double t_now = (double)c->level * c->dt_cl[0];
+  const double cycles = (t - t_now) / sync;
+  const double ncd = std::nearbyint(cycles);
+  if (ncd < 0 || std::fabs(cycles - ncd) > 1e-9 * std::max(1.0, std::fabs(cycles)))
+    return fail(c, EDG_ENOTSYNC, "time is not a synchronisation point after the current time");
+  if (ncd == 0) return EDG_OK;
+  const int64_t nc = (int64_t)ncd;
+  if (c->ckpt_every <= 0) return advance_cycles(c, nc);
+  // checkpointed: segments of at most ckpt_every cycles, each one an advance
+  // of its own that starts from a stored state
+  for (int64_t done = 0; done < nc;) {
+    const int64_t seg = std::min<int64_t>(c->ckpt_every, nc - done);
+    int rc = store_checkpoint(c);
+    if (rc) return rc;
+    if ((rc = advance_cycles(c, seg))) return rc;
+    done += seg;
   }
   return EDG_OK;
 }
@@ -1321,6 +1388,221 @@ int edg_read_receivers(edg_ctx* c, int32_t run, double* out, int64_t cap) {
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipMemcpy(out, (double*)c->r_out.p + (size_t)run * need, need * sizeof(double), hipMemcpyDeviceToHost));
   return EDG_OK;
+}
+
+int edg_set_checkpointing(edg_ctx* c, int32_t every_cycles) {
+  if (!c) return EDG_EINVAL;
+  if (every_cycles < 0) return fail(c, EDG_EINVAL, "negative checkpoint interval");
+  if (every_cycles > 0 && c->runs != 1) return fail(c, EDG_EINVAL, "checkpointing needs a single run");
+  (void)hipSetDevice(c->cfg.device);
+  drop_checkpoints(c);
+  c->ckpt_every = every_cycles;
+  return EDG_OK;
+}
+
+int edg_rewind(edg_ctx* c) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  drop_checkpoints(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (DevBuf* b : {&c->Qe, &c->Qa, &c->T1, &c->T2, &c->T3, &c->RecD, &c->r_out})
+    if (b->p) HIPCHK(c, hipMemset(b->p, 0, b->bytes));
+  HIPCHK(c, hipMemset(c->dclock.p, 0, sizeof(long long)));
+  c->level = 0;
+  for (int l = 0; l < MAX_CLUSTERS; ++l) c->nstep[l] = 0;
+  return EDG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// reverse sweep over the checkpointed segments (see edg_adjoint)
+template <class R, int O, int M>
+int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double* g_q0, double* g_rho, double* g_vp,
+                  double* g_vs) {
+  const int Nc = c->cfg.n_clusters, B = c->B, FP = c->FP, JB = jb_count(c);
+  const size_t rs = sizeof(R), we = c->run_qe, wa = c->run_qa;
+  const size_t slot_words = (size_t)4 * ADJ_ROWS * FP;
+  const int64_t L_end = c->level;
+  const size_t nck = c->ckpts.size();
+  int64_t jmax = 1;
+  for (size_t i = 0; i < nck; ++i) {
+    const int64_t hi = i + 1 < nck ? c->ckpts[i + 1].first : L_end;
+    jmax = std::max(jmax, hi - c->ckpts[i].first);
+  }
+  int rc;
+  const size_t n_hist = (size_t)jmax;   // levels 0 .. J-1 of the longest segment
+  if ((rc = dev_alloc(c, c->aLe, we * rs)) || (rc = dev_alloc(c, c->aLa, std::max<size_t>(wa, 1) * rs)) ||
+      (rc = dev_alloc(c, c->aS1, (size_t)c->Kp * slot_words * rs)) ||
+      (rc = dev_alloc(c, c->aS2, (size_t)c->N2 * slot_words * rs)) ||
+      (rc = dev_alloc(c, c->aS3, (size_t)c->N3 * slot_words * rs)) ||
+      (rc = dev_alloc(c, c->aDe, (size_t)c->G * O * B * EPW * LPE * rs)) ||
+      (rc = dev_alloc(c, c->aDa, std::max<size_t>((size_t)c->G * O * JB * M * 6 * EPW * LPE, 1) * rs)) ||
+      (rc = dev_alloc(c, c->agacc, (size_t)c->Kp * NG * sizeof(double))) ||
+      (rc = dev_alloc(c, c->arecDb, std::max<size_t>(c->run_recd, 1) * rs)) ||
+      (rc = dev_alloc(c, c->aseis, std::max<size_t>((size_t)c->n_rec * c->rec_ns * LPE, 1) * sizeof(double))) ||
+      (rc = dev_alloc(c, c->ahist, n_hist * (we + wa) * rs)) || (rc = dev_alloc(c, c->afinal, (we + wa) * rs)))
+    return rc;
+  for (DevBuf* b : {&c->aLe, &c->aLa, &c->aS1, &c->aS2, &c->aS3, &c->agacc, &c->arecDb, &c->aseis})
+    HIPCHK(c, hipMemset(b->p, 0, b->bytes));
+  if (dj_q && (rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) return rc;
+  if (dj_seis && c->n_rec > 0)
+    HIPCHK(c, hipMemcpy(c->aseis.p, dj_seis, (size_t)c->n_rec * c->rec_ns * LPE * sizeof(double),
+                        hipMemcpyHostToDevice));
+  // keep the final state: the sweep overwrites the DOFs
+  char* fin = (char*)c->afinal.p;
+  HIPCHK(c, hipMemcpy(fin, c->Qe.p, we * rs, hipMemcpyDeviceToDevice));
+  if (wa) HIPCHK(c, hipMemcpy(fin + we * rs, c->Qa.p, wa * rs, hipMemcpyDeviceToDevice));
+
+  const AdvanceArgs A = advance_args(c);
+  const KPtrs p = kptrs(c);
+  APtrs ad;
+  ad.Le = c->aLe.p;
+  ad.La = c->aLa.p;
+  ad.S1 = c->aS1.p;
+  ad.S2 = c->aS2.p;
+  ad.S3 = c->aS3.p;
+  ad.De = c->aDe.p;
+  ad.Da = c->aDa.p;
+  ad.gacc = (double*)c->agacc.p;
+  ad.recDb = c->arecDb.p;
+  const double* seis_b = (const double*)c->aseis.p;
+  char* hist = (char*)c->ahist.p;
+  auto hist_e = [&](int64_t j) { return (void*)(hist + (size_t)j * (we + wa) * rs); };
+  auto hist_a = [&](int64_t j) { return (void*)(hist + ((size_t)j * (we + wa) + we) * rs); };
+  auto chk = [&](int e, const char* what) {
+    return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
+  };
+  for (size_t si = nck; si-- > 0;) {
+    const int64_t L0 = c->ckpts[si].first;
+    const int64_t J = (si + 1 < nck ? c->ckpts[si + 1].first : L_end) - L0;
+    if (J <= 0) continue;
+    // restore the segment's start and replay it forward, keeping the state
+    // at the start of every level's predictions
+    const char* ck = (const char*)c->ckpts[si].second.p;
+    HIPCHK(c, hipMemcpyAsync(c->Qe.p, ck, we * rs, hipMemcpyDeviceToDevice, c->stream));
+    if (wa) HIPCHK(c, hipMemcpyAsync(c->Qa.p, ck + we * rs, wa * rs, hipMemcpyDeviceToDevice, c->stream));
+    const long long clock0 = (long long)L0;
+    HIPCHK(c, hipMemcpyAsync(c->dclock.p, &clock0, sizeof clock0, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    LevelArgs a = base_args(c);
+    a.run0 = 0;
+    for (int64_t j = 0; j < J; ++j) {
+      const int lmax = j == 0 ? Nc - 1 : level_lmax(c, j);
+      a.jrel = (int)j;
+      a.end = c->cl_end[lmax];
+      if (j > 0) {
+        if (c->n_src > 0 && (rc = chk(A.fn.src(p, a, A.sa, c->stream), "source kernel"))) return rc;
+        a.kind = KIND_NEIGHBOR;
+        if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
+      }
+      HIPCHK(c, hipMemcpyAsync(hist_e(j), c->Qe.p, we * rs, hipMemcpyDeviceToDevice, c->stream));
+      if (wa) HIPCHK(c, hipMemcpyAsync(hist_a(j), c->Qa.p, wa * rs, hipMemcpyDeviceToDevice, c->stream));
+      a.kind = KIND_PREDICT;
+      if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
+    }
+    // the levels backwards: transposed predictions, then transposed updates
+    for (int64_t j = J; j >= 0; --j) {
+      const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
+      a.jrel = (int)j;
+      a.end = c->cl_end[lmax];
+      if (j < J) {
+        if (c->n_rec > 0 && dj_seis &&
+            (rc = chk(launch_receivers_adj<R, O, M>(p, ad, a, A.ra, seis_b, c->stream), "receiver adjoint kernel")))
+          return rc;
+        ad.Se = hist_e(j);
+        ad.Sa = hist_a(j);
+        a.kind = KIND_ADJ_PREDICT;
+        if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+      }
+      if (j > 0) {
+        a.kind = KIND_ADJ_UPDATE;
+        if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+      }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  // outputs
+  if (g_q0 && (rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, g_q0))) return rc;
+  if (g_rho || g_vp || g_vs) {
+    std::vector<double> w((size_t)c->Kp * NG);
+    HIPCHK(c, hipMemcpy(w.data(), c->agacc.p, w.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> gr(c->K, 0.0), gp(c->K, 0.0), gsv(c->K, 0.0);
+    // d/d(rho, vp, vs) of the parameters the kernels read, per element
+    auto add = [&](int64_t k, int which, double v) {
+      const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
+      switch (which) {
+        case 0: gr[k] -= v / (rho * rho); break;                                      // 1/rho
+        case 1: gr[k] += v * (vp * vp - 2 * vs * vs); gp[k] += v * 2 * rho * vp; gsv[k] -= v * 4 * rho * vs; break;
+        case 2: gr[k] += v * vs * vs; gsv[k] += v * 2 * rho * vs; break;             // mu
+        case 3: gr[k] += v * vp; gp[k] += v * rho; break;                              // Zp
+        case 4: gr[k] += v * vs; gsv[k] += v * rho; break;                             // Zs
+      }
+    };
+    for (int64_t k = 0; k < c->K; ++k) {
+      const double* x = &w[(size_t)c->user_to_internal[k] * NG];
+      for (int t = 0; t < 5; ++t) add(k, t, x[t]);
+      const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
+      for (int l = 0; l < c->M; ++l) {   // a_l = rho vp^2 Yp - 2 rho vs^2 Ys, b_l = 2 rho vs^2 Ys
+        const double yp = c->yp[k * c->M + l], ys = c->ys[k * c->M + l];
+        const double ga = x[5 + 2 * l], gb = x[6 + 2 * l];
+        gr[k] += ga * (vp * vp * yp - 2 * vs * vs * ys) + gb * 2 * vs * vs * ys;
+        gp[k] += ga * 2 * rho * vp * yp;
+        gsv[k] += -ga * 4 * rho * vs * ys + gb * 4 * rho * vs * ys;
+      }
+      for (int i = 0; i < 4; ++i) {
+        const int64_t n = c->nbr[k * 4 + i];
+        if (n < 0) continue;
+        add(n, 3, x[11 + 2 * i]);         // the neighbour's impedances in the own flux
+        add(n, 4, x[12 + 2 * i]);
+        const double* y = x + 19 + 7 * i; // the neighbour's flux across this face
+        for (int t = 0; t < 5; ++t) add(n, t, y[t]);
+        add(k, 3, y[5]);
+        add(k, 4, y[6]);
+      }
+    }
+    if (g_rho) std::copy(gr.begin(), gr.end(), g_rho);
+    if (g_vp) std::copy(gp.begin(), gp.end(), g_vp);
+    if (g_vs) std::copy(gsv.begin(), gsv.end(), g_vs);
+  }
+  // back to the final state
+  HIPCHK(c, hipMemcpy(c->Qe.p, fin, we * rs, hipMemcpyDeviceToDevice));
+  if (wa) HIPCHK(c, hipMemcpy(c->Qa.p, fin + we * rs, wa * rs, hipMemcpyDeviceToDevice));
+  const long long clock_end = (long long)L_end;
+  HIPCHK(c, hipMemcpy(c->dclock.p, &clock_end, sizeof clock_end, hipMemcpyHostToDevice));
+  return EDG_OK;
+}
+
+typedef int (*AdjFn)(edg_ctx*, const double*, const double*, double*, double*, double*, double*);
+
+AdjFn pick_adjoint(int fp64, int O, int M) {
+  AdjFn f = nullptr;
+#define EDG_PICK_ADJ(R, OO, MM) \
+  if ((std::is_same<R, double>::value == (fp64 != 0)) && O == OO && M == MM) f = &adjoint_sweep<R, OO, MM>;
+  EDG_FOR_EACH_VARIANT(EDG_PICK_ADJ)
+#undef EDG_PICK_ADJ
+  return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int edg_adjoint(edg_ctx* c, const double* dj_dseis, const double* dj_dq, double* g_q0, double* g_rho, double* g_vp,
+                double* g_vs) {
+  if (!c) return EDG_EINVAL;
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (c->runs != 1) return fail(c, EDG_ESTATE, "the adjoint needs a single run");
+  if (c->ckpt_every <= 0 || c->ckpts.empty())
+    return fail(c, EDG_ESTATE, "no checkpoints: enable checkpointing before the forward advance");
+  if (c->ckpts.back().first > c->level) return fail(c, EDG_ESTATE, "checkpoints are ahead of the current time");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  AdjFn f = pick_adjoint(c->cfg.fp64, c->O, c->M);
+  if (!f) return fail(c, EDG_EINVAL, "no adjoint kernel for this order / mechanism count");
+  return f(c, dj_dseis, dj_dq, g_q0, g_rho, g_vp, g_vs);
 }
 
 double edg_time(const edg_ctx* c) { return c ? (double)c->level * c->dt_cl[0] : 0.0; }

@@ -1,0 +1,187 @@
+"""GPU discrete adjoint (edg_adjoint) against the oracle's discrete adjoint on
+the same seeded inputs, plus properties that need no oracle: the dot-product
+identity of the GPU's own forward and adjoint, independence of the checkpoint
+interval, and central differences of a misfit along random material
+directions.
+
+Misfit of the tests: J = <seis, seisbar> + <Q(T), Qbar> for random seisbar,
+Qbar (any differentiable misfit enters only through these two adjoints).
+FP64: the adjoint of the initial DOFs to relative L2 <= 1e-11 per quantity
+group, the material gradients to <= 1e-10 (norm-relative); FP32 runs state
+their errors.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.adjoint import adjoint as oracle_adjoint
+from oracle.solver import Oracle
+from tests.helpers import parity
+
+pytestmark = pytest.mark.gpu
+
+REC = dict(xyz=np.array([[150.0, 170.0, -20.0], [260.0, 300.0, -150.0]]), dt_sample=2e-3, n_samples=40)
+SRC = dict(xyz=np.array([[200.0, 210.0, -90.0]]), moment=np.array([[1e9, -2e9, 0.5e9, 3e9, 1e9, -1e9]]),
+           stf_kind=0, stf_params=np.array([[200.0, 0.004]]))
+TOL64_Q, TOL64_G = 1e-11, 1e-10
+
+
+def _mesh():
+    mesh = synth.layered_box(2, 2, [100.0, 200.0], 400.0, 400.0, jitter=0.15, seed=3)
+    K = mesh["tet_verts"].shape[0]
+    return mesh, synth.random_materials(K, 4)
+
+
+def _distance_clusters(nbr, n_clusters):
+    dist = np.full(nbr.shape[0], -1)
+    dist[0] = 0
+    front = [0]
+    while front:
+        nxt = []
+        for k in front:
+            for j in nbr[k]:
+                if j >= 0 and dist[j] < 0:
+                    dist[j] = dist[k] + 1
+                    nxt.append(j)
+        front = nxt
+    return np.minimum(1 + dist, n_clusters)
+
+
+def _setup(order, mech, n_clusters, fp64, explicit=False):
+    from paper_2202_10313_amd import Context
+    mesh, mat = _mesh()
+    attn = synth.attenuation_inputs(mat, mech, 0.1, 10.0) if mech else None
+    cfl = 0.5 / 2 ** (n_clusters - 1) if explicit else 0.5
+    ctx = Context(order, mechanisms=mech, n_clusters=n_clusters, fp64=fp64, cfl=cfl,
+                  lam=1.0 if explicit else None)
+    ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+    if mech:
+        ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+    else:
+        ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"])
+    cl = None
+    if explicit:
+        probe = Oracle(mesh, mat, 2)
+        cl = _distance_clusters(probe.nbr, n_clusters)
+    ctx.upload_clusters(cl)
+    info = ctx.get_clusters()
+    assert len(np.unique(info["clusters"])) == n_clusters
+    frozen = dict(n_clusters=n_clusters, lam=info["lam"], clusters=info["clusters"], dt_min=info["dt_min"])
+    return ctx, dict(mesh=mesh, mat=mat, attn=attn, order=order, frozen=frozen, sync=info["sync_dt"])
+
+
+def _oracle(w, mat=None, sources=True):
+    return Oracle(w["mesh"], mat or w["mat"], w["order"], attn=w["attn"], receivers=REC,
+                  sources=SRC if sources else None, **w["frozen"])
+
+
+def _inputs(ctx, seed):
+    rng = np.random.default_rng(seed)
+    x = synth.random_state(seed, ctx.K, ctx.nq, ctx.B)
+    y = rng.standard_normal((ctx.K, ctx.nq, ctx.B)) * np.where(np.arange(ctx.nq) < 6, 1e-6, 1.0)[None, :, None]
+    sb = rng.standard_normal((len(REC["xyz"]), REC["n_samples"], 9))
+    return x, y, sb
+
+
+def _run_gpu(ctx, x, y, sb, t, every, sources=True):
+    if sources:
+        ctx.set_sources(SRC["xyz"], SRC["moment"], SRC["stf_kind"], SRC["stf_params"])
+    ctx.set_receivers(REC["xyz"], REC["dt_sample"], REC["n_samples"])
+    ctx.set_checkpointing(every)
+    ctx.set_initial(x)
+    ctx.advance_to(t)
+    qT, seis = ctx.read_dofs(), ctx.read_receivers()
+    res = ctx.adjoint(dj_dseis=sb, dj_dq=y)
+    return qT, seis, res
+
+
+def _grad_err(res, ores):
+    return max(np.linalg.norm(res[k] - ores[k]) / np.linalg.norm(ores[k]) for k in ("g_rho", "g_vp", "g_vs"))
+
+
+@pytest.mark.parametrize("order,mech,n_clusters,explicit,every", [
+    (3, 3, 2, False, 1), (2, 0, 3, True, 2), (4, 3, 2, False, 3), (5, 3, 2, False, 1), (4, 0, 2, False, 1)])
+def test_adjoint_matches_oracle_fp64(order, mech, n_clusters, explicit, every):
+    ctx, w = _setup(order, mech, n_clusters, True, explicit)
+    x, y, sb = _inputs(ctx, order + mech)
+    t = 3 * w["sync"]
+    print(f"[adjoint] O={order} m={mech} Nc={n_clusters} every={every}", flush=True)
+    qT, seis, res = _run_gpu(ctx, x, y, sb, t, every)
+    orc = _oracle(w)
+    orc.set_initial(x)
+    ores = oracle_adjoint(orc, t, seis_b=sb, q_b=y, attn=w["attn"])
+    e_fwd = parity(qT, orc.Q)
+    e_q = parity(res["q0_b"], ores["q0_b"])
+    e_g = _grad_err(res, ores)
+    print(f"[adjoint] FP64 forward {e_fwd:.2e}  adjoint DOFs {e_q:.2e}  gradients {e_g:.2e}", flush=True)
+    assert e_fwd <= 1e-11
+    assert e_q <= TOL64_Q
+    assert e_g <= TOL64_G
+    # the context is back at the final state and time
+    assert ctx.time() == pytest.approx(t, rel=1e-14)
+    assert np.array_equal(ctx.read_dofs(), qT)
+
+
+@pytest.mark.parametrize("order", [4, 5])
+def test_adjoint_matches_oracle_fp32(order):
+    ctx, w = _setup(order, 3, 2, False)
+    x, y, sb = _inputs(ctx, 40 + order)
+    t = 3 * w["sync"]
+    qT, seis, res = _run_gpu(ctx, x, y, sb, t, 1)
+    orc = _oracle(w)
+    orc.set_initial(x)
+    ores = oracle_adjoint(orc, t, seis_b=sb, q_b=y, attn=w["attn"])
+    e_q = parity(res["q0_b"], ores["q0_b"])
+    e_g = _grad_err(res, ores)
+    print(f"[adjoint] FP32 O={order}: adjoint DOFs {e_q:.2e}  gradients {e_g:.2e}", flush=True)
+    assert e_q <= 2e-5
+    assert e_g <= 1e-4
+
+
+def test_dot_product_identity_on_the_gpu():
+    ctx, w = _setup(3, 3, 2, True)
+    x, y, sb = _inputs(ctx, 9)
+    t = 2 * w["sync"]
+    qT, seis, res = _run_gpu(ctx, x, y, sb, t, 1, sources=False)
+    lhs = np.sum(qT * y) + np.sum(seis * sb)
+    rhs = np.sum(x * res["q0_b"])
+    scale = np.sum(np.abs(qT * y)) + np.sum(np.abs(seis * sb))
+    print(f"[adjoint] GPU dot identity {abs(lhs - rhs) / scale:.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+def test_checkpoint_interval_does_not_change_the_result():
+    out = []
+    for every in (1, 4):
+        ctx, w = _setup(3, 3, 2, True)
+        x, y, sb = _inputs(ctx, 11)
+        out.append(_run_gpu(ctx, x, y, sb, 4 * w["sync"], every)[2])
+        ctx.close()
+    assert parity(out[0]["q0_b"], out[1]["q0_b"]) <= 1e-13
+    assert _grad_err(out[0], out[1]) <= 1e-13
+
+
+def test_gradient_matches_central_differences_fp64():
+    ctx, w = _setup(3, 3, 2, True)
+    x, y, sb = _inputs(ctx, 13)
+    t = 3 * w["sync"]
+    _, _, res = _run_gpu(ctx, x, y, sb, t, 1)
+    ctx.set_checkpointing(0)
+    mat, attn = w["mat"], w["attn"]
+
+    def J(m):
+        ctx.upload_materials(m["rho"], m["vp"], m["vs"], attn["omega"], attn["yp"], attn["ys"])
+        ctx.rewind()
+        ctx.set_initial(x)
+        ctx.advance_to(t)
+        return np.sum(ctx.read_dofs() * y) + np.sum(ctx.read_receivers() * sb)
+
+    rng = np.random.default_rng(3)
+    eps, worst = 1e-5, 0.0
+    for _ in range(6):
+        d = {k: rng.standard_normal(ctx.K) * mat[k] for k in ("rho", "vp", "vs")}
+        pred = sum(np.sum(res["g_" + k] * d[k]) for k in ("rho", "vp", "vs"))
+        fd = (J({k: mat[k] + eps * d[k] for k in d}) - J({k: mat[k] - eps * d[k] for k in d})) / (2 * eps)
+        worst = max(worst, abs(pred - fd) / abs(fd))
+    print(f"[adjoint] GPU gradient vs central differences: {worst:.2e}", flush=True)
+    assert worst <= 1e-6
