@@ -81,6 +81,8 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   constexpr int JB = (B + LPE - 1) / LPE;
   __shared__ R lds[L::TOTAL];
   __shared__ double gsh[EPW * NG];
+  // per-lane adjoint of the memory-variable derivatives (time kernel backwards)
+  __shared__ R nmsh[(M > 0 ? JB * MM * 6 : 1) * 64];
 
   const int lane = threadIdx.x;
   const int e = lane / LPE, r = lane % LPE;
@@ -120,50 +122,49 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
     om[l] = M > 0 ? R(a.omega[l]) : R(0);
   }
 
-  // adjoint state: this lane's elastic row, the memory variables of its modes
+  // adjoint state: this lane's elastic row (registers); the memory variables
+  // of its modes are read from memory where they are used (fewer live
+  // registers in the long kernel)
   R le[B];
-  R la[JB][MM][6];
   const size_t gbase = (size_t)g * B;
 #pragma unroll
   for (int b = 0; b < B; ++b) le[b] = Le[(gbase + b) * NSLOT + slot];
-#pragma unroll
-  for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-    for (int l = 0; l < MM; ++l)
-#pragma unroll
-      for (int c = 0; c < 6; ++c)
-        la[jb][l][c] = M > 0 ? La[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+  auto la_at = [&](int jb, int l, int c) -> R& { return La[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot]; };
 
   // omega-weighted memory-variable adjoints per stress component, rows [c][b]
   R* const Cx = reg + L::C;
-  if (M > 0) {
+  auto put_weighted = [&]() {
+    if (M > 0) {
 #pragma unroll
-    for (int jb = 0; jb < JB; ++jb) {
-      const int b = q + LPE * jb;
-      if (b < B && act)
+      for (int jb = 0; jb < JB; ++jb) {
+        const int b = q + LPE * jb;
+        if (b < B && act)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          R w = R(0);
+          for (int c = 0; c < 6; ++c) {
+            R w = R(0);
 #pragma unroll
-          for (int l = 0; l < MM; ++l) w += om[l] * la[jb][l][c];
-          Cx[c * B + b] = w;
-        }
+            for (int l = 0; l < MM; ++l) w += om[l] * la_at(jb, l, c);
+            Cx[c * B + b] = w;
+          }
+      }
     }
-  }
-  __syncthreads();
+  };
   // face adjoints of this lane's rows: elastic row q, memory-variable row 9+q
+  // (the weighted sums must be in Cx)
   R ue[4 * FP], ua[4 * FP];
-  RF::trace(le, ue);
-  {
+  auto face_adjoints = [&]() {
+    RF::trace(le, ue);
     R wrow[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) wrow[b] = (M > 0 && is_stress) ? Cx[q * B + b] : R(0);
     RF::trace(wrow, ua);
-  }
-  __syncthreads();
+  };
 
   // ================================================================ ADJ_UPDATE
   if (a.kind == KIND_ADJ_UPDATE) {
+    put_weighted();
+    __syncthreads();
+    face_adjoints();
     if (!valid) return;
     const int n = step_fin_of(a, cl);
     R* const S1 = reinterpret_cast<R*>(ad.S1);
@@ -342,15 +343,19 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
     }
   }
   __syncthreads();
+  // exchange the adjoints the transposed volume kernel mixes: elastic rows,
+  // and the omega-weighted memory-variable sums (the time kernel above reused
+  // that area)
   if (act)
 #pragma unroll
     for (int b = 0; b < B; ++b) Xr[q * B + b] = le[b];
+  put_weighted();
   __syncthreads();
   {
     // adjoint of the gradient entries of this row (the volume kernel reads
     // the velocity gradients in the stress rows and memory variables, the
     // stress gradients in the velocity rows)
-    R gb[3 * B];
+    R* const gb = grad + q * 3 * B;   // own row of the (now free) gradient area
     if (!is_stress) {
       const int i = q - 6;
 #pragma unroll
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
         for (int b = 0; b < B; ++b) {
           R v = -fm * mu * Xr[sk * B + b] - (M > 0 ? fa * Cx[sk * B + b] : R(0));
           if (i == k) v -= lam * (Xr[0 * B + b] + Xr[1 * B + b] + Xr[2 * B + b]);
-          gb[k * B + b] = v;
+          if (act) gb[k * B + b] = v;
         }
       }
     } else {
@@ -372,11 +377,13 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
         if (k == qj) iv = qi;
         else if (k == qi) iv = qj;
 #pragma unroll
-        for (int b = 0; b < B; ++b) gb[k * B + b] = iv >= 0 ? -rho_inv * Xr[(6 + iv) * B + b] : R(0);
+        for (int b = 0; b < B; ++b)
+          if (act) gb[k * B + b] = iv >= 0 ? -rho_inv * Xr[(6 + iv) * B + b] : R(0);
       }
     }
     RF::vol_grad_T(gb, G, lte);
   }
+  face_adjoints();
   __syncthreads();
 
   // ---------------------------------------------- B. own surface part
@@ -520,15 +527,17 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
 
   // ---------------------------------------------- E. time kernel backwards
   R nbe[B];                 // adjoint of D_{d+1} (elastic row)
-  R nbm[JB][MM][6];         // adjoint of D_{d+1} (memory variables)
+  // adjoint of D_{d+1} (memory variables of the owned modes), lane-private LDS
+  auto nbm = [&](int jb, int l, int c) -> R& { return nmsh[((jb * MM + l) * 6 + c) * 64 + lane]; };
 #pragma unroll
   for (int b = 0; b < B; ++b) nbe[b] = R(0);
+  if (M > 0)
 #pragma unroll
-  for (int jb = 0; jb < JB; ++jb)
+    for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-    for (int l = 0; l < MM; ++l)
+      for (int l = 0; l < MM; ++l)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) nbm[jb][l][c] = R(0);
+        for (int c = 0; c < 6; ++c) nbm(jb, l, c) = R(0);
   R* const recDb = reinterpret_cast<R*>(ad.recDb);
 #pragma unroll 1
   for (int d = O - 1; d >= 0; --d) {
@@ -584,13 +593,13 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
             for (int c = 0; c < 6; ++c) {
               R w = R(0);
 #pragma unroll
-              for (int l = 0; l < MM; ++l) w += om[l] * nbm[jb][l][c];
+              for (int l = 0; l < MM; ++l) w += om[l] * nbm(jb, l, c);
               Cx[c * B + b] = w;
             }
         }
       }
       __syncthreads();
-      R gb[3 * B];
+      R* const gb = grad + q * 3 * B;   // own row of the (now free) gradient area
       if (!is_stress) {
         const int i = q - 6;
 #pragma unroll
@@ -601,7 +610,7 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
           for (int b = 0; b < B; ++b) {
             R v = fm * mu * Xr[sk * B + b] + (M > 0 ? fa * Cx[sk * B + b] : R(0));
             if (i == k) v += lam * (Xr[0 * B + b] + Xr[1 * B + b] + Xr[2 * B + b]);
-            gb[k * B + b] = v;
+            if (act) gb[k * B + b] = v;
           }
         }
       } else {
@@ -611,7 +620,8 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
           if (k == qj) iv = qi;
           else if (k == qi) iv = qj;
 #pragma unroll
-          for (int b = 0; b < B; ++b) gb[k * B + b] = iv >= 0 ? rho_inv * Xr[(6 + iv) * B + b] : R(0);
+          for (int b = 0; b < B; ++b)
+            if (act) gb[k * B + b] = iv >= 0 ? rho_inv * Xr[(6 + iv) * B + b] : R(0);
         }
       }
       RF::ck_grad_T(gb, G, cur);
@@ -651,9 +661,9 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
             for (int c = 0; c < 6; ++c) {
               // -omega_l c_d T^a volume term, -omega_l theta in the next
               // derivative, coupling into the stresses
-              R v = -om[l] * c_d * la[jb][l][c] - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
-              if (more) v -= om[l] * nbm[jb][l][c];
-              nbm[jb][l][c] = v;
+              R v = -om[l] * c_d * la_at(jb, l, c) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
+              if (more) v -= om[l] * nbm(jb, l, c);
+              nbm(jb, l, c) = v;
             }
           }
         }
@@ -665,12 +675,6 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   }
 #pragma unroll
   for (int b = 0; b < B; ++b) le[b] += nbe[b];
-#pragma unroll
-  for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-    for (int l = 0; l < MM; ++l)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) la[jb][l][c] += nbm[jb][l][c];
   if (valid) {
 #pragma unroll
     for (int b = 0; b < B; ++b) Le[(gbase + b) * NSLOT + slot] = le[b];
@@ -680,7 +684,7 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
 #pragma unroll
         for (int l = 0; l < MM; ++l)
 #pragma unroll
-          for (int c = 0; c < 6; ++c) La[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = la[jb][l][c];
+          for (int c = 0; c < 6; ++c) la_at(jb, l, c) += nbm(jb, l, c);
   }
   __syncthreads();
   if (valid)
