@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fused-runs", type=int, default=16, help="runs of the fused batch line (<= 1: skip it)")
     ap.add_argument("--fused-steps", type=int, default=4)
+    ap.add_argument("--adjoint-steps", type=int, default=2,
+                    help="cycles of the forward + adjoint (gradient) line (0: skip it)")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch every level eagerly")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false", help="keep the default launch plan")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -203,6 +205,41 @@ def main():
         ctx.close()
         return res
 
+    def measure_adjoint(order, steps):
+        """Gradient of J = 1/2 sum_r,s |seis|^2 dt_sample with respect to rho,
+        vp, vs over `steps` LTS cycles: the checkpointed forward (a checkpoint
+        per cycle) plus the reverse sweep (replay of each cycle from its
+        checkpoint, adjoint kernels backwards).  One untimed cycle first."""
+        ctx = Context(order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream)
+        ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+        ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+        ctx.upload_clusters(None)
+        sync = ctx.get_clusters()["sync_dt"]
+        # t0 = 0: the source radiates from the first step, so the gradient of
+        # the short window is not zero
+        ctx.set_sources(src["xyz"], src["moment"], STF_RICKER, np.array([[2.0, 0.0]]))
+        dts = 0.005
+        ctx.set_receivers(rec, dts, int((steps + 2) * sync / dts) + 2)
+        ctx.set_checkpointing(1)
+        out = {}
+        for phase, n in (("warm", 1), ("timed", steps)):
+            ctx.rewind()
+            ctx.set_initial(np.zeros((K, ctx.nq, ctx.B)))
+            u0 = ctx.element_updates()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.advance_to(n * sync)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = ctx.adjoint(dj_dseis=ctx.read_receivers() * dts, want_q0=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out = dict(updates=ctx.element_updates() - u0, fwd=t1 - t0, adj=t2 - t1)
+        if not all(np.all(np.isfinite(g[k])) for k in ("g_rho", "g_vp", "g_vs")):
+            raise RuntimeError("non-finite gradient")
+        ctx.close()
+        return out
+
     print(f"[bench] plain: 1 run, O={args.order}, warmup {args.warmup}, {args.steps} cycles", file=sys.stderr, flush=True)
     m = measure(args.order, 1, args.steps, args.warmup)
     info, ks, wall, updates = m["info"], m["ks"], m["wall"], m["updates"]
@@ -257,6 +294,21 @@ def main():
                  "launch_plan": f["plan"],
                  "sources": "one Ricker per run: fc U[1,3] Hz, random moment tensor, uniform in the top 5 km"}
         print(f"[bench] fused: {fv:.4g} run-element updates/s ({fv / value:.2f}x plain)", file=sys.stderr, flush=True)
+    adjoint = None
+    if args.adjoint_steps > 0:
+        print(f"[bench] forward + adjoint: O={args.order}, {args.adjoint_steps} cycles", file=sys.stderr, flush=True)
+        a = measure_adjoint(args.order, args.adjoint_steps)
+        wall_plain = wall / args.steps * args.adjoint_steps          # plain forward of the same cycles
+        av = a["updates"] / (a["fwd"] + a["adj"])
+        adjoint = {"value": av, "unit": "elem-updates/s (forward updates per second of forward + gradient)",
+                   "steps": args.adjoint_steps, "ms_per_step": (a["fwd"] + a["adj"]) * 1e3 / args.adjoint_steps,
+                   "forward_checkpointed_ms": a["fwd"] * 1e3, "reverse_sweep_ms": a["adj"] * 1e3,
+                   "cost_vs_plain_forward": (a["fwd"] + a["adj"]) / wall_plain,
+                   "reverse_vs_plain_forward": a["adj"] / wall_plain,
+                   "checkpoint_every_cycles": 1,
+                   "misfit": "1/2 sum |seismogram|^2 dt_sample over the 64 receivers; gradient w.r.t. rho, vp, vs"}
+        print(f"[bench] forward + adjoint: {av:.4g} element updates/s, {adjoint['cost_vs_plain_forward']:.2f}x the "
+              f"plain forward", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": value,
@@ -277,12 +329,13 @@ def main():
             "lambda": info["lam"], "cluster_sizes": counts.tolist(),
             "theoretical_lts_speedup": info["speedup"],
             "gts_equivalent_rate": K * (args.steps * sync / info["dt_min"]) / wall,
-            "adjoint": "not built",
         },
         "roofline": roofline,
     }
     if fused is not None:
         out["fused"] = fused
+    if adjoint is not None:
+        out["adjoint"] = adjoint
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -72,17 +72,23 @@ struct AdjLds {
 // adds v to the element's gradient word w (LDS, FP64)
 __device__ __forceinline__ void gadd(double* gs, int w, double v) { atomicAdd(gs + w, v); }
 
-template <class R, int O, int M>
+// UPD: the transposed update (KIND_ADJ_UPDATE) only needs the weighted
+// memory-variable rows in LDS, so it is its own instantiation with a small
+// LDS footprint (more workgroups per CU).
+template <class R, int O, int M, bool UPD>
 __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
   using RF = edg_gen::Ref<O>;
   using L = AdjLds<R, O, M>;
   constexpr int B = RF::B, F = RF::F, FP = RF::FP;
   constexpr int MM = M > 0 ? M : 1;
   constexpr int JB = (B + LPE - 1) / LPE;
-  __shared__ R lds[L::TOTAL];
-  __shared__ double gsh[EPW * NG];
-  // per-lane adjoint of the memory-variable derivatives (time kernel backwards)
-  __shared__ R nmsh[(M > 0 ? JB * MM * 6 : 1) * 64];
+  // FP32 keeps the memory-variable derivative adjoints in registers; FP64
+  // (twice the registers) keeps them in lane-private LDS
+  constexpr bool NM_LDS = sizeof(R) == 8 && M > 0 && !UPD;
+  constexpr int RSTRIDE = UPD ? 6 * B : L::REGION;   // LDS words per element
+  __shared__ R lds[EPW * RSTRIDE];
+  __shared__ double gsh[UPD ? 1 : EPW * NG];
+  __shared__ R nmsh[(NM_LDS ? JB * MM * 6 : 1) * 64];
 
   const int lane = threadIdx.x;
   const int e = lane / LPE, r = lane % LPE;
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   const int cl = cluster_of(a, g * EPW);
   const bool valid = act && (elem < a.cl_vend[cl]);
   const int slot = ec * LPE + q;
-  R* const reg = lds + ec * L::REGION;
+  R* const reg = lds + ec * RSTRIDE;
   double* const gs = gsh + ec * NG;
   const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
   const int* FI = p.FI + (size_t)elem * FI_WORDS;
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   auto la_at = [&](int jb, int l, int c) -> R& { return La[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot]; };
 
   // omega-weighted memory-variable adjoints per stress component, rows [c][b]
-  R* const Cx = reg + L::C;
+  R* const Cx = reg + (UPD ? 0 : L::C);
   auto put_weighted = [&]() {
     if (M > 0) {
 #pragma unroll
@@ -161,7 +167,7 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   };
 
   // ================================================================ ADJ_UPDATE
-  if (a.kind == KIND_ADJ_UPDATE) {
+  if constexpr (UPD) {
     put_weighted();
     __syncthreads();
     face_adjoints();
@@ -528,7 +534,11 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   // ---------------------------------------------- E. time kernel backwards
   R nbe[B];                 // adjoint of D_{d+1} (elastic row)
   // adjoint of D_{d+1} (memory variables of the owned modes), lane-private LDS
-  auto nbm = [&](int jb, int l, int c) -> R& { return nmsh[((jb * MM + l) * 6 + c) * 64 + lane]; };
+  R nbm_r[NM_LDS ? 1 : JB][MM][6];
+  auto nbm = [&](int jb, int l, int c) -> R& {
+    if constexpr (NM_LDS) return nmsh[((jb * MM + l) * 6 + c) * 64 + lane];
+    else return nbm_r[jb][l][c];
+  };
 #pragma unroll
   for (int b = 0; b < B; ++b) nbe[b] = R(0);
   if (M > 0)
@@ -735,7 +745,10 @@ template <class R, int O, int M>
 int launch_adjoint(const KPtrs& p, const APtrs& ad, const LevelArgs& a, hipStream_t st) {
   const int groups = (a.end + EPW - 1) / EPW;
   if (groups <= 0) return 0;
-  hipLaunchKernelGGL((k_adjoint<R, O, M>), dim3(groups), dim3(64), 0, st, p, ad, a);
+  if (a.kind == KIND_ADJ_UPDATE)
+    hipLaunchKernelGGL((k_adjoint<R, O, M, true>), dim3(groups), dim3(64), 0, st, p, ad, a);
+  else
+    hipLaunchKernelGGL((k_adjoint<R, O, M, false>), dim3(groups), dim3(64), 0, st, p, ad, a);
   return (int)hipGetLastError();
 }
 

@@ -154,6 +154,12 @@ int dev_alloc(edg_ctx* c, DevBuf& b, size_t bytes) {
   return 0;
 }
 
+// keeps b if it already holds at least `bytes` (buffers reused across calls)
+int dev_reserve(edg_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.p && b.bytes >= bytes) return 0;
+  return dev_alloc(c, b, bytes);
+}
+
 int dev_upload(edg_ctx* c, DevBuf& b, const void* src, size_t bytes) {
   int rc = dev_alloc(c, b, bytes);
   if (rc) return rc;
@@ -1434,19 +1440,23 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   }
   int rc;
   const size_t n_hist = (size_t)jmax;   // levels 0 .. J-1 of the longest segment
-  if ((rc = dev_alloc(c, c->aLe, we * rs)) || (rc = dev_alloc(c, c->aLa, std::max<size_t>(wa, 1) * rs)) ||
-      (rc = dev_alloc(c, c->aS1, (size_t)c->Kp * slot_words * rs)) ||
-      (rc = dev_alloc(c, c->aS2, (size_t)c->N2 * slot_words * rs)) ||
-      (rc = dev_alloc(c, c->aS3, (size_t)c->N3 * slot_words * rs)) ||
-      (rc = dev_alloc(c, c->aDe, (size_t)c->G * O * B * EPW * LPE * rs)) ||
-      (rc = dev_alloc(c, c->aDa, std::max<size_t>((size_t)c->G * O * JB * M * 6 * EPW * LPE, 1) * rs)) ||
-      (rc = dev_alloc(c, c->agacc, (size_t)c->Kp * NG * sizeof(double))) ||
-      (rc = dev_alloc(c, c->arecDb, std::max<size_t>(c->run_recd, 1) * rs)) ||
-      (rc = dev_alloc(c, c->aseis, std::max<size_t>((size_t)c->n_rec * c->rec_ns * LPE, 1) * sizeof(double))) ||
-      (rc = dev_alloc(c, c->ahist, n_hist * (we + wa) * rs)) || (rc = dev_alloc(c, c->afinal, (we + wa) * rs)))
+  if ((rc = dev_reserve(c, c->aLe, we * rs)) || (rc = dev_reserve(c, c->aLa, std::max<size_t>(wa, 1) * rs)) ||
+      (rc = dev_reserve(c, c->aS1, (size_t)c->Kp * slot_words * rs)) ||
+      (rc = dev_reserve(c, c->aS2, (size_t)c->N2 * slot_words * rs)) ||
+      (rc = dev_reserve(c, c->aS3, (size_t)c->N3 * slot_words * rs)) ||
+      (rc = dev_reserve(c, c->aDe, (size_t)c->G * O * B * EPW * LPE * rs)) ||
+      (rc = dev_reserve(c, c->aDa, std::max<size_t>((size_t)c->G * O * JB * M * 6 * EPW * LPE, 1) * rs)) ||
+      (rc = dev_reserve(c, c->agacc, (size_t)c->Kp * NG * sizeof(double))) ||
+      (rc = dev_reserve(c, c->arecDb, std::max<size_t>(c->run_recd, 1) * rs)) ||
+      (rc = dev_reserve(c, c->aseis, std::max<size_t>((size_t)c->n_rec * c->rec_ns * LPE, 1) * sizeof(double))) ||
+      (rc = dev_reserve(c, c->ahist, n_hist * (we + wa) * rs)) || (rc = dev_reserve(c, c->afinal, (we + wa) * rs)))
     return rc;
+  // the slots and receiver derivatives return to zero at the end of every
+  // sweep (each is cleared by its reader); they are cleared here for the
+  // first use and after a failed sweep
   for (DevBuf* b : {&c->aLe, &c->aLa, &c->aS1, &c->aS2, &c->aS3, &c->agacc, &c->arecDb, &c->aseis})
-    HIPCHK(c, hipMemset(b->p, 0, b->bytes));
+    HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   if (dj_q && (rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) return rc;
   if (dj_seis && c->n_rec > 0)
     HIPCHK(c, hipMemcpy(c->aseis.p, dj_seis, (size_t)c->n_rec * c->rec_ns * LPE * sizeof(double),

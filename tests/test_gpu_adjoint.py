@@ -178,10 +178,107 @@ def test_gradient_matches_central_differences_fp64():
 
     rng = np.random.default_rng(3)
     eps, worst = 1e-5, 0.0
-    for _ in range(6):
+    for _ in range(20):
         d = {k: rng.standard_normal(ctx.K) * mat[k] for k in ("rho", "vp", "vs")}
         pred = sum(np.sum(res["g_" + k] * d[k]) for k in ("rho", "vp", "vs"))
         fd = (J({k: mat[k] + eps * d[k] for k in d}) - J({k: mat[k] - eps * d[k] for k in d})) / (2 * eps)
         worst = max(worst, abs(pred - fd) / abs(fd))
     print(f"[adjoint] GPU gradient vs central differences: {worst:.2e}", flush=True)
     assert worst <= 1e-6
+
+
+def test_autograd_misfit_gradient():
+    """torch.autograd through the library: the L2 misfit between the
+    seismograms and data from a model perturbed by +-3% per element; the
+    gradient equals the oracle's discrete adjoint for the same seismogram
+    adjoint and central differences of the misfit."""
+    import torch
+    from paper_2202_10313_amd.autograd import Simulation
+    ctx, w = _setup(3, 3, 2, True)
+    ctx.set_sources(SRC["xyz"], SRC["moment"], SRC["stf_kind"], SRC["stf_params"])
+    ctx.set_receivers(REC["xyz"], REC["dt_sample"], REC["n_samples"])
+    t = 3 * w["sync"]
+    mat, attn = w["mat"], w["attn"]
+    x = synth.random_state(21, ctx.K, ctx.nq, ctx.B)
+    sim = Simulation(ctx, t, attn["omega"], attn["yp"], attn["ys"], q0=x)
+    dev = "cuda"
+    rng = np.random.default_rng(17)
+    pert = {k: mat[k] * (1 + rng.uniform(-0.03, 0.03, ctx.K)) for k in ("rho", "vp", "vs")}
+    with torch.no_grad():
+        d = sim.seismograms(*(torch.tensor(pert[k], device=dev) for k in ("rho", "vp", "vs")))
+    dt = REC["dt_sample"]
+
+    def misfit(m, grad=False):
+        ps = [torch.tensor(m[k], device=dev, requires_grad=grad) for k in ("rho", "vp", "vs")]
+        s = sim.seismograms(*ps)
+        return 0.5 * ((s - d) ** 2).sum() * dt, s, ps
+
+    J, s, ps = misfit(mat, grad=True)
+    J.backward()
+    g = {k: p.grad.cpu().numpy() for k, p in zip(("rho", "vp", "vs"), ps)}
+    orc = _oracle(w)
+    orc.set_initial(x)
+    ores = oracle_adjoint(orc, t, seis_b=((s - d) * dt).detach().cpu().numpy(), attn=attn)
+    e = max(np.linalg.norm(g[k] - ores["g_" + k]) / np.linalg.norm(ores["g_" + k]) for k in g)
+    worst = 0.0
+    eps = 1e-5
+    for _ in range(3):
+        dd = {k: rng.standard_normal(ctx.K) * mat[k] for k in g}
+        pred = sum(np.sum(g[k] * dd[k]) for k in g)
+        with torch.no_grad():
+            fd = (misfit({k: mat[k] + eps * dd[k] for k in g})[0] - misfit({k: mat[k] - eps * dd[k] for k in g})[0])
+        fd = float(fd) / (2 * eps)
+        worst = max(worst, abs(pred - fd) / abs(fd))
+    print(f"[adjoint] autograd: vs oracle {e:.2e}, vs central differences {worst:.2e}", flush=True)
+    assert e <= TOL64_G
+    assert worst <= 1e-6
+
+
+@pytest.mark.parametrize("mech", [0, 3])
+def test_adjoint_5k_tets_order4(mech):
+    """The oracle-sized mesh of the differentiation workload (2 x 2 x 1 km
+    layered box, 5,082 tets, O = 4, N_c = 2, 32 surface receivers): misfit
+    against data from a +-3% perturbed model, GPU adjoint (FP64) against the
+    oracle's discrete adjoint over two LTS cycles."""
+    from tests.helpers import anelastic_setup, gpu_context
+    w = anelastic_setup("small", 4, 2, with_source=True, n_rec=32)
+    attn = w["attn"] if mech else None
+    mat = w["mat"]
+    ctx = gpu_context(w, 4, 2, True, mechanisms=mech)
+    info = ctx.get_clusters()
+    assert len(np.unique(info["clusters"])) == 2
+    K, nq = ctx.K, ctx.nq
+    x = synth.random_state(35, K, nq, ctx.B)
+    dts, ns = 2.5e-4, 20
+    ctx.set_sources(w["src"]["xyz"], w["src"]["moment"], w["src"]["stf_kind"], w["src"]["stf_params"])
+    ctx.set_receivers(w["rec"], dts, ns)
+    t = 2 * info["sync_dt"]
+    # data from the perturbed model (same clusters and steps)
+    rng = np.random.default_rng(55)
+    pert = {k: mat[k] * (1 + rng.uniform(-0.03, 0.03, K)) for k in ("rho", "vp", "vs")}
+    extra = (attn["omega"], attn["yp"], attn["ys"]) if mech else ()
+    ctx.upload_materials(pert["rho"], pert["vp"], pert["vs"], *extra)
+    ctx.set_initial(x)
+    ctx.advance_to(t)
+    d = ctx.read_receivers()
+    ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], *extra)
+    ctx.rewind()
+    ctx.set_checkpointing(1)
+    ctx.set_initial(x)
+    ctx.advance_to(t)
+    s = ctx.read_receivers()
+    sb = (s - d) * dts
+    res = ctx.adjoint(dj_dseis=sb)
+    print(f"[adjoint] 5k tets O=4 m={mech}: running the oracle adjoint", flush=True)
+    orc = Oracle(w["mesh"], mat, 4, attn=attn, n_clusters=2, lam=info["lam"], clusters=info["clusters"],
+                 dt_min=info["dt_min"], sources=w["src"], receivers=dict(xyz=w["rec"], dt_sample=dts, n_samples=ns))
+    orc.set_initial(x)
+    ores = oracle_adjoint(orc, t, seis_b=sb, attn=attn)
+    e_s = np.linalg.norm(orc.seis - s) / np.linalg.norm(orc.seis)
+    e_q = parity(res["q0_b"], ores["q0_b"])
+    e_g = _grad_err(res, ores)
+    print(f"[adjoint] 5k tets O=4 m={mech} FP64: seismograms {e_s:.2e} adjoint DOFs {e_q:.2e} gradients {e_g:.2e}",
+          flush=True)
+    assert e_s <= 1e-11
+    assert e_q <= TOL64_Q
+    assert e_g <= TOL64_G
