@@ -53,7 +53,7 @@ PAPER_FLOPS_ALL_SPARSITY = 212688
 # on (their SHA-256 below); after any change the roofline reports null.
 TRAFFIC_BYTES_PER_UPDATE = 15327.1
 TRAFFIC_SOURCES_SHA256 = "265f0dcb93db8ac018da16f9b35bb837213505a965b8a79ea28fab85fdbc5ee2"
-KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
+KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "device_common.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
 
 

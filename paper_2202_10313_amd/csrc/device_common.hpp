@@ -96,162 +96,6 @@ __host__ __device__ __forceinline__ void godunov(const R* qm, const R* qp, R nx,
   out[14] = hs * (nx * vz + nz * vx);
 }
 
-// Reverse mode of godunov(): for the adjoint u of its 15 outputs, adds
-// (d out / d qm)^T u to qm_b, (d out / d qp)^T u to qp_b (interior faces) and
-// the derivatives of <u, out> in (rho_inv, lam, mu, zpm, zsm, zpp, zsp) to
-// pb[0..6].  out is linear in (qm, qp), so the parameter derivatives are
-// bilinear: they use the states passed in (zeros for a side that another
-// element accounts for).
-template <class R>
-__host__ __device__ __forceinline__ void godunov_adj(const R* u, const R* qm, const R* qp, R nx, R ny, R nz, R zpm,
-                                                     R zsm, R zpp, R zsp, R lam, R mu, R rho_inv, R s, int bc,
-                                                     R* qm_b, R* qp_b, R* pb) {
-  const R n[3] = {nx, ny, nz};
-  // forward intermediates
-  R tm[3], vm[3], tp[3], vp[3];
-  tm[0] = qm[0] * nx + qm[3] * ny + qm[5] * nz;
-  tm[1] = qm[3] * nx + qm[1] * ny + qm[4] * nz;
-  tm[2] = qm[5] * nx + qm[4] * ny + qm[2] * nz;
-  vm[0] = qm[6]; vm[1] = qm[7]; vm[2] = qm[8];
-  if (bc == 0) {
-    tp[0] = qp[0] * nx + qp[3] * ny + qp[5] * nz;
-    tp[1] = qp[3] * nx + qp[1] * ny + qp[4] * nz;
-    tp[2] = qp[5] * nx + qp[4] * ny + qp[2] * nz;
-    vp[0] = qp[6]; vp[1] = qp[7]; vp[2] = qp[8];
-  } else if (bc == 1) {
-    for (int c = 0; c < 3; ++c) { tp[c] = -tm[c]; vp[c] = vm[c]; }
-  } else {
-    for (int c = 0; c < 3; ++c) { tp[c] = R(0); vp[c] = R(0); }
-  }
-  const R tnm = tm[0] * nx + tm[1] * ny + tm[2] * nz, vnm = vm[0] * nx + vm[1] * ny + vm[2] * nz;
-  const R tnp = tp[0] * nx + tp[1] * ny + tp[2] * nz, vnp = vp[0] * nx + vp[1] * ny + vp[2] * nz;
-  const R ip = R(1) / (zpm + zpp), is = R(1) / (zsm + zsp);
-  const R Y = zpm * vnm + zpp * vnp + tnp - tnm;
-  const R Z = zpp * tnm + zpm * tnp + zpm * zpp * (vnp - vnm);
-  const R vn = Y * ip, tn = Z * ip;
-  const R zz = zsm * zsp;
-  R tTm[3], vTm[3], tTp[3], vTp[3], W[3], X[3], v[3], t[3];
-  for (int c = 0; c < 3; ++c) {
-    tTm[c] = tm[c] - tnm * n[c];
-    vTm[c] = vm[c] - vnm * n[c];
-    tTp[c] = tp[c] - tnp * n[c];
-    vTp[c] = vp[c] - vnp * n[c];
-    W[c] = zsm * vTm[c] + zsp * vTp[c] + tTp[c] - tTm[c];
-    X[c] = zsp * tTm[c] + zsm * tTp[c] + zz * (vTp[c] - vTm[c]);
-    v[c] = vn * n[c] + W[c] * is;
-    t[c] = tn * n[c] + X[c] * is;
-  }
-  // outputs -> v, t, material parameters
-  R vb[3] = {R(0), R(0), R(0)}, tb[3] = {R(0), R(0), R(0)};
-  R vnb = R(0), lamb = R(0), mub = R(0), rib = R(0);
-  const R hs = R(0.5) * s;
-  for (int c = 0; c < 3; ++c) {
-    vnb += s * lam * u[c];
-    lamb += s * vn * u[c];
-    vb[c] += R(2) * mu * s * n[c] * u[c];
-    mub += R(2) * s * n[c] * v[c] * u[c];
-    tb[c] += s * rho_inv * u[6 + c];
-    rib += s * t[c] * u[6 + c];
-    vb[c] += s * n[c] * u[9 + c];
-  }
-  const int pa[3] = {0, 1, 0}, pc[3] = {1, 2, 2};   // (x,y), (y,z), (x,z)
-  for (int k = 0; k < 3; ++k) {
-    const int a = pa[k], b = pc[k];
-    const R ue = u[3 + k], ua = u[12 + k];
-    vb[b] += mu * s * n[a] * ue + hs * n[a] * ua;
-    vb[a] += mu * s * n[b] * ue + hs * n[b] * ua;
-    mub += s * (n[a] * v[b] + n[b] * v[a]) * ue;
-  }
-  // v = vn n + W is, t = tn n + X is
-  R Wb[3], Xb[3];
-  R isb = R(0), tnb = R(0);
-  for (int c = 0; c < 3; ++c) {
-    vnb += vb[c] * n[c];
-    tnb += tb[c] * n[c];
-    Wb[c] = vb[c] * is;
-    Xb[c] = tb[c] * is;
-    isb += vb[c] * W[c] + tb[c] * X[c];
-  }
-  R vTmb[3], vTpb[3], tTmb[3], tTpb[3];
-  R zsmb = R(0), zspb = R(0), zzb = R(0);
-  for (int c = 0; c < 3; ++c) {
-    vTmb[c] = zsm * Wb[c] - zz * Xb[c];
-    vTpb[c] = zsp * Wb[c] + zz * Xb[c];
-    tTpb[c] = Wb[c] + zsm * Xb[c];
-    tTmb[c] = -Wb[c] + zsp * Xb[c];
-    zsmb += Wb[c] * vTm[c] + Xb[c] * tTp[c];
-    zspb += Wb[c] * vTp[c] + Xb[c] * tTm[c];
-    zzb += Xb[c] * (vTp[c] - vTm[c]);
-  }
-  zsmb += zsp * zzb;
-  zspb += zsm * zzb;
-  // tangential parts
-  R tmb[3], vmb[3], tpb[3], vpb[3];
-  R tnmb = R(0), vnmb = R(0), tnpb = R(0), vnpb = R(0);
-  for (int c = 0; c < 3; ++c) {
-    tmb[c] = tTmb[c];
-    vmb[c] = vTmb[c];
-    tpb[c] = tTpb[c];
-    vpb[c] = vTpb[c];
-    tnmb -= tTmb[c] * n[c];
-    vnmb -= vTmb[c] * n[c];
-    tnpb -= tTpb[c] * n[c];
-    vnpb -= vTpb[c] * n[c];
-  }
-  // normal parts
-  const R Yb = vnb * ip, Zb = tnb * ip;
-  const R ipb = vnb * Y + tnb * Z;
-  vnmb += zpm * Yb - zpm * zpp * Zb;
-  vnpb += zpp * Yb + zpm * zpp * Zb;
-  tnpb += Yb + zpm * Zb;
-  tnmb += -Yb + zpp * Zb;
-  R zpmb = Yb * vnm + Zb * (tnp + zpp * (vnp - vnm));
-  R zppb = Yb * vnp + Zb * (tnm + zpm * (vnp - vnm));
-  zpmb -= ipb * ip * ip;
-  zppb -= ipb * ip * ip;
-  zsmb -= isb * is * is;
-  zspb -= isb * is * is;
-  for (int c = 0; c < 3; ++c) {
-    tmb[c] += tnmb * n[c];
-    vmb[c] += vnmb * n[c];
-    tpb[c] += tnpb * n[c];
-    vpb[c] += vnpb * n[c];
-  }
-  // outside state
-  if (bc == 0) {
-    qp_b[0] += tpb[0] * nx;
-    qp_b[1] += tpb[1] * ny;
-    qp_b[2] += tpb[2] * nz;
-    qp_b[3] += tpb[0] * ny + tpb[1] * nx;
-    qp_b[4] += tpb[1] * nz + tpb[2] * ny;
-    qp_b[5] += tpb[0] * nz + tpb[2] * nx;
-    qp_b[6] += vpb[0];
-    qp_b[7] += vpb[1];
-    qp_b[8] += vpb[2];
-  } else if (bc == 1) {
-    for (int c = 0; c < 3; ++c) {
-      tmb[c] -= tpb[c];
-      vmb[c] += vpb[c];
-    }
-  }
-  qm_b[0] += tmb[0] * nx;
-  qm_b[1] += tmb[1] * ny;
-  qm_b[2] += tmb[2] * nz;
-  qm_b[3] += tmb[0] * ny + tmb[1] * nx;
-  qm_b[4] += tmb[1] * nz + tmb[2] * ny;
-  qm_b[5] += tmb[0] * nz + tmb[2] * nx;
-  qm_b[6] += vmb[0];
-  qm_b[7] += vmb[1];
-  qm_b[8] += vmb[2];
-  pb[0] += rib;
-  pb[1] += lamb;
-  pb[2] += mub;
-  pb[3] += zpmb;
-  pb[4] += zsmb;
-  pb[5] += zppb;
-  pb[6] += zspb;
-}
-
 // Steps of cluster cl at the processed level (see LevelArgs::clock).
 __device__ __forceinline__ int step_new_of(const LevelArgs& a, int cl) {
   return (int)((*a.clock + a.jrel) >> cl);

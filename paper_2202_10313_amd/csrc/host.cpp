@@ -18,6 +18,7 @@
 #include "basis.hpp"
 #include "edge_lts.h"
 #include "kernels.hpp"
+#include "adjoint.hpp"
 
 using namespace edg;
 
