@@ -329,6 +329,18 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
     face_adjoints();
     if (!valid) return;
     const int n = step_fin_of(a, cl);
+    {
+      // the own-flux face adjoints of this step, for the two-wave transposed
+      // prediction (the Qbar it reads is unchanged until then)
+      R* const S0 = reinterpret_cast<R*>(ad.S0) + (size_t)elem * sstride;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) {
+          S0[(i * ADJ_ROWS + q) * FP + f] = ue[i * FP + f];
+          if (is_stress) S0[(i * ADJ_ROWS + 9 + q) * FP + f] = ua[i * FP + f];
+        }
+    }
     R* const S1 = reinterpret_cast<R*>(ad.S1);
     R* const S2 = reinterpret_cast<R*>(ad.S2);
     R* const S3 = reinterpret_cast<R*>(ad.S3);
@@ -857,6 +869,590 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
     for (int w = q; w < NG; w += LPE) ad.gacc[(size_t)elem * NG + w] += gsh[ec * NG + w];
 }
 
+// ---------------------------------------------------------------------------
+// Two-wave transposed prediction (FP32, O = 4, 5): a workgroup of two waves
+// owns 7 elements, wave w keeps the modes [MB_w, MB_{w+1}) of every row (as
+// the forward k_level2), so the per-lane state halves and two waves fit per
+// SIMD.  Whole rows for the reference-matrix products come from the LDS row
+// exchange; products write or read physical-gradient slots (the 18 (row,
+// direction) pairs the star products use); the face data of the element's
+// own flux come from S0 (written by the transposed update of the same step),
+// so no face adjoint is formed here.
+template <class R, int O, int M>
+struct AdjLds2 {
+  using RF = edg_gen::Ref<O>;
+  static constexpr int B = RF::B, FP = RF::FP;
+  static constexpr int up(int v, int m, int r) { return v + ((r - v % m) % m + m) % m; }
+  static constexpr int BS = B % 2 ? B : B + 1;       // odd row stride
+  static constexpr int FS = FP + 1;
+  static constexpr int NSL = 20;                     // 18 read pairs, unread dummy 18, zero row 19
+  static constexpr int GRAD = NSL * BS;
+  static constexpr int COUP = 6 * BS;
+  static constexpr int RX = LPE * BS;
+  static constexpr int PMW = 4 * LPE * FS;           // face traces / their adjoints [face][row][f]
+  static constexpr int REST = GRAD + COUP + RX;
+  static constexpr int REGION = up(REST > PMW + RX ? REST : PMW + RX, 32, (9 * BS) % 32);
+  static constexpr int TOTAL = EPW * REGION;
+};
+
+// (row, direction) -> gradient slot: velocity rows all directions, stress row
+// (i, j) directions i and j; 18 = not read, 19 = zeros
+__device__ __forceinline__ int aslot(int row, int dir) {
+  constexpr int T[9][3] = {{9, 18, 18}, {18, 10, 18}, {18, 18, 11}, {12, 13, 18}, {18, 14, 15},
+                           {16, 18, 17}, {0, 1, 2}, {3, 4, 5}, {6, 7, 8}};
+  return T[row][dir];
+}
+
+template <class R, int O, int M>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
+  using RF = edg_gen::Ref<O>;
+  using L = AdjLds2<R, O, M>;
+  constexpr int B = RF::B, F = RF::F, FP = RF::FP;
+  constexpr int MM = M > 0 ? M : 1;
+  constexpr int NB0 = RF::MB1, NB1 = B - RF::MB1;
+  constexpr int NBX = NB0 > NB1 ? NB0 : NB1;
+  constexpr int JW = (NBX + LPE - 1) / LPE;      // owned memory modes per lane
+  constexpr int JB = (B + LPE - 1) / LPE;        // memory-variable layout
+  constexpr int BS = L::BS, FS = L::FS;
+  __shared__ R lds[L::TOTAL];
+  __shared__ double gsh[EPW * NG];
+
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int e = lane / LPE, r = lane % LPE;
+  const bool act = e < EPW;
+  const int ec = act ? e : EPW - 1;
+  const int q = act ? r : 0;
+  const int g = blockIdx.x;
+  const int elem = g * EPW + ec;
+  const int cl = cluster_of(a, g * EPW);
+  const bool valid = act && (elem < a.cl_vend[cl]);
+  const int slot = ec * LPE + q;
+  const int base = w ? RF::MB1 : 0;
+  const int nb = w ? NB1 : NB0;
+  R* const reg = lds + ec * L::REGION;
+  R* const grad = reg;
+  R* const coup = reg + L::GRAD;
+  R* const rx = reg + L::GRAD + L::COUP;
+  R* const pm = reg;                               // face area (overlaps grad / coup)
+  double* const gs = gsh + ec * NG;
+  const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
+  const int* FI = p.FI + (size_t)elem * FI_WORDS;
+  R* const Le = reinterpret_cast<R*>(ad.Le) + (size_t)g * B * NSLOT;
+  R* const La = reinterpret_cast<R*>(ad.La) + (size_t)g * JB * MM * 6 * NSLOT;
+  R* const De = reinterpret_cast<R*>(ad.De) + (size_t)g * O * B * NSLOT;
+  R* const Da = reinterpret_cast<R*>(ad.Da) + (size_t)g * O * JB * MM * 6 * NSLOT;
+  const size_t sstride = (size_t)4 * ADJ_ROWS * FP;
+
+  const bool is_stress = q < 6;
+  int qi = 0, qj = 0;
+  if (q < 3) { qi = q; qj = q; }
+  else if (q == 3) { qi = 0; qj = 1; }
+  else if (q == 4) { qi = 1; qj = 2; }
+  else if (q == 5) { qi = 0; qj = 2; }
+  const R delta = q < 3 ? R(1) : R(0);
+
+  R G[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) G[c] = P[c];
+  const R rho_inv = P[9], lam = P[10], mu = P[11], zp = P[12], zs = P[13];
+  R al[MM], bl[MM], om[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    al[l] = M > 0 ? P[14 + 2 * l] : R(0);
+    bl[l] = M > 0 ? P[15 + 2 * l] : R(0);
+    om[l] = M > 0 ? R(a.omega[l]) : R(0);
+  }
+  // gradient slots this lane writes (forward products) and the star-product
+  // reads: stress row ij: lam delta div v + mu (d_j v_i + d_i v_j);
+  // velocity row i: rho_inv sum_d d_d sigma_id
+  R* const gw0 = grad + aslot(q, 0) * BS;
+  R* const gw1 = grad + aslot(q, 1) * BS;
+  R* const gw2 = grad + aslot(q, 2) * BS;
+  int sa, sb, sc, sd, se;
+  if (is_stress) {
+    sa = aslot(6, 0) * BS; sb = aslot(7, 1) * BS; sc = aslot(8, 2) * BS;
+    sd = aslot(6 + qi, qj) * BS; se = aslot(6 + qj, qi) * BS;
+  } else {
+    const int i = q - 6;
+    sa = aslot(sym_index(i, 0), 0) * BS; sb = aslot(sym_index(i, 1), 1) * BS; sc = aslot(sym_index(i, 2), 2) * BS;
+    sd = sa; se = sb;
+  }
+  // transposed products read this row's gradient adjoints: the used slots, else zeros
+  const R* const gt0 = grad + (aslot(q, 0) == 18 ? 19 : aslot(q, 0)) * BS;
+  const R* const gt1 = grad + (aslot(q, 1) == 18 ? 19 : aslot(q, 1)) * BS;
+  const R* const gt2 = grad + (aslot(q, 2) == 18 ? 19 : aslot(q, 2)) * BS;
+
+  for (int i = threadIdx.x; i < EPW * NG; i += 128) gsh[i] = 0.0;
+
+  const int nn = step_new_of(a, cl);
+  const int eflags = FI[12];
+  const bool has_b2 = (eflags & EF_HAS_FINER) != 0;
+  const bool has_b3 = (eflags & EF_HAS_COARSER) != 0;
+  const bool any_b2 = __syncthreads_or(has_b2);
+  const int rec_slot = FI[15];
+
+  // ---------------------------------------------- forward recompute: D_d, T, T2
+  R te[NBX], t2[NBX];
+  {
+    const R* Se = reinterpret_cast<const R*>(ad.Se) + (size_t)g * B * NSLOT;
+    const R* Sa = reinterpret_cast<const R*>(ad.Sa) + (size_t)g * JB * MM * 6 * NSLOT;
+    R dm[JW][MM][6];
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) {
+      te[lb] = R(0);
+      t2[lb] = R(0);
+      if (lb < nb && act) rx[q * BS + base + lb] = Se[(base + lb) * NSLOT + slot];
+    }
+#pragma unroll
+    for (int jw = 0; jw < JW; ++jw) {
+      const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) dm[jw][l][c] = (M > 0 && lb < nb) ? Sa[((jb * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+    }
+#pragma unroll 1
+    for (int d = 0; d < O; ++d) {
+      const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
+      const bool more = d + 1 < O;
+      __syncthreads();
+      {
+        R dv[NBX];
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) dv[lb] = lb < nb ? rx[q * BS + base + lb] : R(0);
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) { te[lb] += c_d * dv[lb]; t2[lb] += h_d * dv[lb]; }
+        if (valid) {
+#pragma unroll
+          for (int lb = 0; lb < NBX; ++lb)
+            if (lb < nb) De[((size_t)d * B + base + lb) * NSLOT + slot] = dv[lb];
+          if (M > 0)
+#pragma unroll
+            for (int jw = 0; jw < JW; ++jw) {
+              const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+              if (lb < nb)
+#pragma unroll
+                for (int l = 0; l < MM; ++l)
+#pragma unroll
+                  for (int c = 0; c < 6; ++c) Da[((((size_t)d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = dm[jw][l][c];
+            }
+        }
+      }
+      if (!more) break;
+      {
+        R full[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+        if (w == 0) RF::ck_grad_p0(full, G, gw0, gw1, gw2);
+        else RF::ck_grad_p1(full, G, gw0, gw1, gw2);
+      }
+      __syncthreads();
+      if (M > 0) {
+#pragma unroll
+        for (int jw = 0; jw < JW; ++jw) {
+          const int lb = q + LPE * jw, b = base + lb;
+          if (lb < nb) {
+            R eps[6];
+            eps[0] = grad[aslot(6, 0) * BS + b];
+            eps[1] = grad[aslot(7, 1) * BS + b];
+            eps[2] = grad[aslot(8, 2) * BS + b];
+            eps[3] = R(0.5) * (grad[aslot(6, 1) * BS + b] + grad[aslot(7, 0) * BS + b]);
+            eps[4] = R(0.5) * (grad[aslot(7, 2) * BS + b] + grad[aslot(8, 1) * BS + b]);
+            eps[5] = R(0.5) * (grad[aslot(6, 2) * BS + b] + grad[aslot(8, 0) * BS + b]);
+            R cp[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int l = 0; l < MM; ++l) {
+              const R tr = dm[jw][l][0] + dm[jw][l][1] + dm[jw][l][2];
+#pragma unroll
+              for (int c = 0; c < 6; ++c) cp[c] -= bl[l] * dm[jw][l][c] + (c < 3 ? al[l] * tr : R(0));
+#pragma unroll
+              for (int c = 0; c < 6; ++c) dm[jw][l][c] = om[l] * (eps[c] - dm[jw][l][c]);
+            }
+            if (act)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) coup[c * BS + b] = cp[c];
+          }
+        }
+        __syncthreads();
+      }
+      // next derivative, own modes, into the row exchange
+      {
+        R nx[NBX];
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) {
+          const int b = base + lb;
+          if (lb < nb) {
+            if (is_stress) {
+              const R cq = M > 0 ? coup[q * BS + b] : R(0);
+              nx[lb] = lam * delta * (grad[sa + b] + grad[sb + b] + grad[sc + b]) + mu * (grad[sd + b] + grad[se + b]) + cq;
+            } else {
+              nx[lb] = rho_inv * (grad[sa + b] + grad[sb + b] + grad[sc + b]);
+            }
+          }
+        }
+        __syncthreads();
+        if (act)
+#pragma unroll
+          for (int lb = 0; lb < NBX; ++lb)
+            if (lb < nb) rx[q * BS + base + lb] = nx[lb];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------- face phases
+  // The element's traces (full rows through the row exchange, each wave the
+  // traces of faces 2w, 2w+1), then per (face, face mode) the Godunov reverse
+  // mode, then the lift of the trace adjoints to the wave's modes.
+  R lte[NBX], lt2[NBX];
+#pragma unroll
+  for (int lb = 0; lb < NBX; ++lb) { lte[lb] = R(0); lt2[lb] = R(0); }
+  R* const S0 = reinterpret_cast<R*>(ad.S0);
+  R* const S1 = reinterpret_cast<R*>(ad.S1);
+  R* const S2 = reinterpret_cast<R*>(ad.S2);
+  R* const S3 = reinterpret_cast<R*>(ad.S3);
+  auto face_phase = [&](const bool b2phase, const R* tint, R* acc) {
+    if (act)
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb)
+        if (lb < nb) rx[q * BS + base + lb] = tint[lb];
+    __syncthreads();
+    {
+      R full[B], pt[2 * FP];
+#pragma unroll
+      for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+      if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
+      if (act)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int f = 0; f < FP; ++f) pm[((2 * w + ii) * LPE + q) * FS + f] = pt[ii * FP + f];
+    }
+    __syncthreads();
+    // items (face i, mode f), spread over both waves' lanes of the element
+#pragma unroll 1
+    for (int rr = 0; rr < (4 * F + 2 * LPE - 1) / (2 * LPE); ++rr) {
+      const int t = q + LPE * (w + 2 * rr);
+      if (t < 4 * F && act) {
+        const int i = t / F, f = t % F;
+        const int code = FI[3 * i + 1];
+        const int bc = (code >> 4) & 15;
+        const int nbr = FI[3 * i];
+        R tr[9], zero9[9], tb[9], ob[9], pb[7];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { tr[k] = pm[(i * LPE + k) * FS + f]; zero9[k] = R(0); tb[k] = R(0); ob[k] = R(0); }
+        if (!b2phase) {
+          // own flux: the element's trace is the inside state
+          const R* u0 = S0 + (size_t)elem * sstride + (size_t)i * ADJ_ROWS * FP + f;
+          R u[15];
+#pragma unroll
+          for (int k = 0; k < 15; ++k) u[k] = (M > 0 || k < 9) ? u0[k * FP] : R(0);
+          const R* fp = P + 20 + 6 * i;
+#pragma unroll
+          for (int k = 0; k < 7; ++k) pb[k] = R(0);
+          const R zpp = bc == 0 ? fp[4] : zp, zsp = bc == 0 ? fp[5] : zs;
+          godunov_adj<R>(u, tr, zero9, fp[0], fp[1], fp[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fp[3], bc, tb, ob, pb);
+          if (valid) {
+            gadd(gs, 0, pb[0]);
+            gadd(gs, 1, pb[1]);
+            gadd(gs, 2, pb[2]);
+            gadd(gs, 3, pb[3]);
+            gadd(gs, 4, pb[4]);
+            gadd(gs, bc == 0 ? 11 + 2 * i : 3, pb[5]);
+            gadd(gs, bc == 0 ? 12 + 2 * i : 4, pb[6]);
+          }
+        }
+        if (nbr >= 0 && valid) {
+          // the neighbour's flux reads this element's buffer: B1 (+ B3) or B2
+          R* s1 = b2phase ? (has_b2 ? S2 + (size_t)FI[13] * sstride : nullptr) : S1 + (size_t)elem * sstride;
+          R* s3 = (!b2phase && has_b3) ? S3 + (size_t)FI[14] * sstride : nullptr;
+          R u[15];
+#pragma unroll
+          for (int k = 0; k < 15; ++k) u[k] = R(0);
+          if (s1) {
+            R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
+#pragma unroll
+            for (int k = 0; k < 15; ++k) { u[k] += x[k * FP]; x[k * FP] = R(0); }
+          }
+          if (s3) {
+            R* x = s3 + (size_t)i * ADJ_ROWS * FP + f;
+            const bool clear3 = (nn & 1) == 0;
+#pragma unroll
+            for (int k = 0; k < 15; ++k) { u[k] += x[k * FP]; if (clear3) x[k * FP] = R(0); }
+          }
+          if (M == 0)
+#pragma unroll
+            for (int k = 9; k < 15; ++k) u[k] = R(0);
+          const int j = code & 15;
+          const R* Pn = reinterpret_cast<const R*>(p.P) + (size_t)nbr * NPARAM;
+          const R* fn = Pn + 20 + 6 * j;
+#pragma unroll
+          for (int k = 0; k < 7; ++k) pb[k] = R(0);
+          godunov_adj<R>(u, zero9, tr, fn[0], fn[1], fn[2], Pn[12], Pn[13], fn[4], fn[5], Pn[10], Pn[11], Pn[9], fn[3], 0,
+                         ob, tb, pb);
+#pragma unroll
+          for (int k = 0; k < 7; ++k) gadd(gs, 19 + 7 * i + k, pb[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pm[(i * LPE + k) * FS + f] = tb[k];
+      }
+    }
+    __syncthreads();
+    {
+      R pf[4 * FP];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) pf[i * FP + f] = pm[(i * LPE + q) * FS + f];
+      if (w == 0) RF::lift_p0(pf, acc); else RF::lift_p1(pf, acc);
+    }
+    __syncthreads();
+  };
+  if (any_b2) face_phase(true, t2, lt2);
+  face_phase(false, te, lte);
+
+  // ---------------------------------------------- volume kernel
+  // V = -(lam delta div v + mu (d_j v_i + d_i v_j)) (stress), -rho_inv div sigma (velocity), -omega_l eps (memory)
+  R le[NBX];
+#pragma unroll
+  for (int lb = 0; lb < NBX; ++lb) le[lb] = lb < nb ? Le[(base + lb) * NSLOT + slot] : R(0);
+  auto la_at = [&](int jb, int l, int c) -> R& { return La[((jb * MM + l) * 6 + c) * NSLOT + slot]; };
+  if (act)
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) rx[q * BS + base + lb] = te[lb];
+  __syncthreads();
+  {
+    R full[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+    if (w == 0) RF::vol_grad_p0(full, G, gw0, gw1, gw2);
+    else RF::vol_grad_p1(full, G, gw0, gw1, gw2);
+  }
+  if (threadIdx.x < 64 && act)      // zero row for the transposed products (written once, never overwritten)
+    for (int b = q; b < BS; b += LPE) grad[19 * BS + b] = R(0);
+  __syncthreads();
+  // star-product adjoint pairings with the forward gradients: dV/dlam, dV/dmu, dV/drho_inv
+  auto star_grams = [&](const R* ad_own, const double sign) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) {
+      const int b = base + lb;
+      if (lb < nb) {
+        const R abc = grad[sa + b] + grad[sb + b] + grad[sc + b];
+        if (is_stress) {
+          s0 += (double)(ad_own[lb] * abc);
+          s1 += (double)(ad_own[lb] * (grad[sd + b] + grad[se + b]));
+        } else {
+          s0 += (double)(ad_own[lb] * abc);
+        }
+      }
+    }
+    if (valid) {
+      if (is_stress) {
+        if (q < 3) gadd(gs, 1, sign * s0);
+        gadd(gs, 2, sign * s1);
+      } else {
+        gadd(gs, 0, sign * s0);
+      }
+    }
+  };
+  star_grams(le, -1.0);
+  __syncthreads();
+  // exchange: elastic adjoint rows, omega-weighted memory-variable adjoints
+  if (act)
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) rx[q * BS + base + lb] = le[lb];
+  if (M > 0) {
+#pragma unroll
+    for (int jw = 0; jw < JW; ++jw) {
+      const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+      if (lb < nb && act)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          R v = R(0);
+#pragma unroll
+          for (int l = 0; l < MM; ++l) v += om[l] * la_at(jb, l, c);
+          coup[c * BS + b] = v;
+        }
+    }
+  }
+  __syncthreads();
+  // gradient-entry adjoints of this row, own modes, into its slots (sign s:
+  // -1 for the volume kernel, +1 for the time kernel's next derivative)
+  auto write_gb = [&](const R sgn) {
+    if (!act) return;
+    if (!is_stress) {
+      const int i = q - 6;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int sk = sym_index(i, k);
+        const R fm = i == k ? R(2) : R(1), fa = i == k ? R(1) : R(0.5);
+        R* dst = grad + aslot(q, k) * BS;
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) {
+          const int b = base + lb;
+          if (lb < nb) {
+            R v = fm * mu * rx[sk * BS + b] + (M > 0 ? fa * coup[sk * BS + b] : R(0));
+            if (i == k) v += lam * (rx[0 * BS + b] + rx[1 * BS + b] + rx[2 * BS + b]);
+            dst[b] = sgn * v;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        int iv = -1;
+        if (k == qj) iv = qi;
+        else if (k == qi) iv = qj;
+        if (iv < 0) continue;
+        R* dst = grad + aslot(q, k) * BS;
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb) {
+          const int b = base + lb;
+          if (lb < nb) dst[b] = sgn * rho_inv * rx[(6 + iv) * BS + b];
+        }
+      }
+    }
+  };
+  write_gb(R(-1));
+  __syncthreads();
+  if (w == 0) RF::vol_grad_T_p0(gt0, gt1, gt2, G, lte);
+  else RF::vol_grad_T_p1(gt0, gt1, gt2, G, lte);
+  __syncthreads();
+
+  // ---------------------------------------------- time kernel backwards
+  R nbe[NBX];
+  R nbm[JW][MM][6];
+#pragma unroll
+  for (int lb = 0; lb < NBX; ++lb) nbe[lb] = R(0);
+#pragma unroll
+  for (int jw = 0; jw < JW; ++jw)
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nbm[jw][l][c] = R(0);
+  R* const recDb = reinterpret_cast<R*>(ad.recDb);
+#pragma unroll 1
+  for (int d = O - 1; d >= 0; --d) {
+    const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
+    const bool more = d + 1 < O;
+    R cur[NBX];
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) cur[lb] = c_d * lte[lb] + h_d * lt2[lb];
+    if (rec_slot >= 0 && valid) {
+      R* rd = recDb + (((size_t)rec_slot * O + d) * LPE + q) * B + base;
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb)
+        if (lb < nb) { cur[lb] += rd[lb]; rd[lb] = R(0); }
+    }
+    if (more) {
+      // forward gradients of D_d for the material pairings
+      if (act)
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb)
+          if (lb < nb) rx[q * BS + base + lb] = De[((size_t)d * B + base + lb) * NSLOT + slot];
+      __syncthreads();
+      {
+        R full[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+        if (w == 0) RF::ck_grad_p0(full, G, gw0, gw1, gw2);
+        else RF::ck_grad_p1(full, G, gw0, gw1, gw2);
+      }
+      __syncthreads();
+      star_grams(nbe, 1.0);
+      __syncthreads();
+      if (act)
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb)
+          if (lb < nb) rx[q * BS + base + lb] = nbe[lb];
+      if (M > 0) {
+#pragma unroll
+        for (int jw = 0; jw < JW; ++jw) {
+          const int lb = q + LPE * jw, b = base + lb;
+          if (lb < nb && act)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              R v = R(0);
+#pragma unroll
+              for (int l = 0; l < MM; ++l) v += om[l] * nbm[jw][l][c];
+              coup[c * BS + b] = v;
+            }
+        }
+      }
+      __syncthreads();
+      write_gb(R(1));
+      __syncthreads();
+      if (w == 0) RF::ck_grad_T_p0(gt0, gt1, gt2, G, cur);
+      else RF::ck_grad_T_p1(gt0, gt1, gt2, G, cur);
+      __syncthreads();
+    }
+    if (M > 0) {
+      // the coupling E: cq_d enters the volume term c_d cq_d and the next derivative
+      if (is_stress && act)
+#pragma unroll
+        for (int lb = 0; lb < NBX; ++lb)
+          if (lb < nb) rx[q * BS + base + lb] = c_d * le[lb] + (more ? nbe[lb] : R(0));
+      __syncthreads();
+#pragma unroll
+      for (int jw = 0; jw < JW; ++jw) {
+        const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+        if (lb < nb) {
+          R cqb[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) cqb[c] = rx[c * BS + b];
+          const R cqt = cqb[0] + cqb[1] + cqb[2];
+#pragma unroll
+          for (int l = 0; l < MM; ++l) {
+            R dmd[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) dmd[c] = Da[((((size_t)d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot];
+            const R tr = dmd[0] + dmd[1] + dmd[2];
+            double ga = -(double)(cqt * tr), gbb = 0.0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) gbb -= (double)(cqb[c] * dmd[c]);
+            if (valid) {
+              gadd(gs, 5 + 2 * l, ga);
+              gadd(gs, 6 + 2 * l, gbb);
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              R v = -om[l] * c_d * la_at(jb, l, c) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
+              if (more) v -= om[l] * nbm[jw][l][c];
+              nbm[jw][l][c] = v;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) nbe[lb] = cur[lb];
+  }
+  if (valid) {
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) Le[(base + lb) * NSLOT + slot] = le[lb] + nbe[lb];
+    if (M > 0)
+#pragma unroll
+      for (int jw = 0; jw < JW; ++jw) {
+        const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+        if (lb < nb)
+#pragma unroll
+          for (int l = 0; l < MM; ++l)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) la_at(jb, l, c) += nbm[jw][l][c];
+      }
+  }
+  __syncthreads();
+  if (valid && w == 0)
+    for (int i = q; i < NG; i += LPE) ad.gacc[(size_t)elem * NG + i] += gsh[ec * NG + i];
+}
+
 // adjoint of the receiver samples: the derivatives of the receiver slots get
 // sum_s (t_s - t^n)^d / d! * seisbar_s phi(x_r) for the samples in the step
 // that starts at this level
@@ -903,6 +1499,8 @@ int launch_adjoint(const KPtrs& p, const APtrs& ad, const LevelArgs& a, hipStrea
   if (groups <= 0) return 0;
   if (a.kind == KIND_ADJ_UPDATE)
     hipLaunchKernelGGL((k_adjoint<R, O, M, true>), dim3(groups), dim3(64), 0, st, p, ad, a);
+  else if constexpr (std::is_same<R, float>::value && O >= 4)
+    hipLaunchKernelGGL((k_adjoint2<R, O, M>), dim3(groups), dim3(128), 0, st, p, ad, a);
   else
     hipLaunchKernelGGL((k_adjoint<R, O, M, false>), dim3(groups), dim3(64), 0, st, p, ad, a);
   return (int)hipGetLastError();

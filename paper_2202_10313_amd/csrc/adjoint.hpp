@@ -21,6 +21,7 @@ struct APtrs {
   void* La;          // adjoint of the memory variables (Qa layout)
   const void* Se;    // forward state at the start of the step (Qe layout)
   const void* Sa;    // (Qa layout)
+  void* S0;          // [Kp][4][15][FP] face adjoints of the element's own flux (its last finished step)
   void* S1;          // [Kp][4][15][FP] adjoint face data for the element's B1 (per own face)
   void* S2;          // [N2][4][15][FP] for B2
   void* S3;          // [N3][4][15][FP] for B3

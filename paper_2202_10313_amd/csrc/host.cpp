@@ -106,7 +106,7 @@ struct edg_ctx {
   int ckpt_every = 0;
   std::vector<std::pair<int64_t, DevBuf>> ckpts;    // (level, Qe then Qa of run 0)
   // adjoint buffers
-  DevBuf aLe, aLa, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal;
+  DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal;
 
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -710,7 +710,7 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
 
 edg_ctx::~edg_ctx() {
   for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
-                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock, &aLe, &aLa, &aS1, &aS2, &aS3, &aDe, &aDa,
+                    &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock, &aLe, &aLa, &aS0, &aS1, &aS2, &aS3, &aDe, &aDa,
                     &agacc, &arecDb, &aseis, &ahist, &afinal})
     dev_free(*b);
   for (auto& ck : ckpts) dev_free(ck.second);
@@ -1442,6 +1442,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   int rc;
   const size_t n_hist = (size_t)jmax;   // levels 0 .. J-1 of the longest segment
   if ((rc = dev_reserve(c, c->aLe, we * rs)) || (rc = dev_reserve(c, c->aLa, std::max<size_t>(wa, 1) * rs)) ||
+      (rc = dev_reserve(c, c->aS0, (size_t)c->Kp * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS1, (size_t)c->Kp * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS2, (size_t)c->N2 * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS3, (size_t)c->N3 * slot_words * rs)) ||
@@ -1455,7 +1456,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   // the slots and receiver derivatives return to zero at the end of every
   // sweep (each is cleared by its reader); they are cleared here for the
   // first use and after a failed sweep
-  for (DevBuf* b : {&c->aLe, &c->aLa, &c->aS1, &c->aS2, &c->aS3, &c->agacc, &c->arecDb, &c->aseis})
+  for (DevBuf* b : {&c->aLe, &c->aLa, &c->aS0, &c->aS1, &c->aS2, &c->aS3, &c->agacc, &c->arecDb, &c->aseis})
     HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (dj_q && (rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) return rc;
@@ -1472,6 +1473,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   APtrs ad;
   ad.Le = c->aLe.p;
   ad.La = c->aLa.p;
+  ad.S0 = c->aS0.p;
   ad.S1 = c->aS1.p;
   ad.S2 = c->aS2.p;
   ad.S3 = c->aS3.p;
