@@ -1453,6 +1453,57 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     for (int i = q; i < NG; i += LPE) ad.gacc[(size_t)elem * NG + i] += gsh[ec * NG + i];
 }
 
+// Chain rule from the per-element gradient words to d/d(rho, vp, vs), one
+// thread per element (internal order), gathering what the face neighbours
+// accumulated about this element.  mat [Kp][3 + 2m]: rho, vp, vs, Yp_l, Ys_l
+// (rho = 0 marks padding).  out [Kp][3].
+__device__ __forceinline__ void add_param(double* g, int which, double v, double rho, double vp, double vs) {
+  switch (which) {
+    case 0: g[0] -= v / (rho * rho); break;                                              // 1/rho
+    case 1: g[0] += v * (vp * vp - 2 * vs * vs); g[1] += v * 2 * rho * vp; g[2] -= v * 4 * rho * vs; break;  // lam
+    case 2: g[0] += v * vs * vs; g[2] += v * 2 * rho * vs; break;                        // mu
+    case 3: g[0] += v * vp; g[1] += v * rho; break;                                       // Zp
+    default: g[0] += v * vs; g[2] += v * rho; break;                                      // Zs
+  }
+}
+
+__global__ void k_material_gradient(const double* gacc, const int* FI, const double* mat, int M, long long Kp,
+                                    double* out) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kp) return;
+  const int mw = 3 + 2 * M;
+  const double rho = mat[k * mw], vp = mat[k * mw + 1], vs = mat[k * mw + 2];
+  double g[3] = {0.0, 0.0, 0.0};
+  if (rho > 0.0) {
+    const double* x = gacc + k * NG;
+    for (int t = 0; t < 5; ++t) add_param(g, t, x[t], rho, vp, vs);
+    for (int l = 0; l < M; ++l) {   // a_l = rho vp^2 Yp - 2 rho vs^2 Ys, b_l = 2 rho vs^2 Ys
+      const double yp = mat[k * mw + 3 + 2 * l], ys = mat[k * mw + 4 + 2 * l];
+      const double ga = x[5 + 2 * l], gb = x[6 + 2 * l];
+      g[0] += ga * (vp * vp * yp - 2 * vs * vs * ys) + gb * 2 * vs * vs * ys;
+      g[1] += ga * 2 * rho * vp * yp;
+      g[2] += -ga * 4 * rho * vs * ys + gb * 4 * rho * vs * ys;
+    }
+    const int* fi = FI + k * FI_WORDS;
+    for (int i = 0; i < 4; ++i) {
+      const int n = fi[3 * i];
+      if (n < 0) continue;
+      const int j = fi[3 * i + 1] & 15;          // the neighbour's face towards this element
+      const double* y = x + 19 + 7 * i;          // this element's Zp, Zs in the neighbour's flux
+      add_param(g, 3, y[5], rho, vp, vs);
+      add_param(g, 4, y[6], rho, vp, vs);
+      const double* xn = gacc + (long long)n * NG;
+      add_param(g, 3, xn[11 + 2 * j], rho, vp, vs);   // this element's impedances in the neighbour's own flux
+      add_param(g, 4, xn[12 + 2 * j], rho, vp, vs);
+      const double* yn = xn + 19 + 7 * j;             // this element's own flux, accumulated by the neighbour
+      for (int t = 0; t < 5; ++t) add_param(g, t, yn[t], rho, vp, vs);
+    }
+  }
+  out[k * 3] = g[0];
+  out[k * 3 + 1] = g[1];
+  out[k * 3 + 2] = g[2];
+}
+
 // adjoint of the receiver samples: the derivatives of the receiver slots get
 // sum_s (t_s - t^n)^d / d! * seisbar_s phi(x_r) for the samples in the step
 // that starts at this level
@@ -1512,6 +1563,14 @@ int launch_receivers_adj(const KPtrs& p, const APtrs& ad, const LevelArgs& a, co
   if (r.n <= 0) return 0;
   const int total = r.n * LPE;
   hipLaunchKernelGGL((k_receivers_adj<R, O, M>), dim3((total + 127) / 128), dim3(128), 0, st, p, ad, a, r, seis_b);
+  return (int)hipGetLastError();
+}
+
+int launch_material_gradient(const double* gacc, const int* FI, const double* mat, int M, long long Kp, double* out,
+                             hipStream_t st) {
+  if (Kp <= 0) return 0;
+  hipLaunchKernelGGL(k_material_gradient, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, st, gacc, FI, mat, M, Kp,
+                     out);
   return (int)hipGetLastError();
 }
 

@@ -31,6 +31,11 @@ struct APtrs {
   void* recDb;       // [slots][O][9][B] adjoint of the receiver derivatives
 };
 
+// d/d(rho, vp, vs) [Kp][3] from the gradient words (mat [Kp][3 + 2m]: rho,
+// vp, vs, Yp_l, Ys_l in internal order; rho = 0 for padding)
+int launch_material_gradient(const double* gacc, const int* FI, const double* mat, int M, long long Kp, double* out,
+                             hipStream_t st);
+
 template <class R, int O, int M>
 int launch_adjoint(const KPtrs& p, const APtrs& ad, const LevelArgs& a, hipStream_t st);
 template <class R, int O, int M>

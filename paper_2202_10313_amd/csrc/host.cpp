@@ -106,7 +106,7 @@ struct edg_ctx {
   int ckpt_every = 0;
   std::vector<std::pair<int64_t, DevBuf>> ckpts;    // (level, Qe then Qa of run 0)
   // adjoint buffers
-  DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal;
+  DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal, amat, agrad;
 
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -711,7 +711,7 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
 edg_ctx::~edg_ctx() {
   for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
                     &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock, &aLe, &aLa, &aS0, &aS1, &aS2, &aS3, &aDe, &aDa,
-                    &agacc, &arecDb, &aseis, &ahist, &afinal})
+                    &agacc, &arecDb, &aseis, &ahist, &afinal, &amat, &agrad})
     dev_free(*b);
   for (auto& ck : ckpts) dev_free(ck.second);
   for (auto& e : ev_pool) {
@@ -1540,45 +1540,36 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   // outputs
   if (g_q0 && (rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, g_q0))) return rc;
   if (g_rho || g_vp || g_vs) {
-    std::vector<double> w((size_t)c->Kp * NG);
-    HIPCHK(c, hipMemcpy(w.data(), c->agacc.p, w.size() * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<double> gr(c->K, 0.0), gp(c->K, 0.0), gsv(c->K, 0.0);
-    // d/d(rho, vp, vs) of the parameters the kernels read, per element
-    auto add = [&](int64_t k, int which, double v) {
-      const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
-      switch (which) {
-        case 0: gr[k] -= v / (rho * rho); break;                                      // 1/rho
-        case 1: gr[k] += v * (vp * vp - 2 * vs * vs); gp[k] += v * 2 * rho * vp; gsv[k] -= v * 4 * rho * vs; break;
-        case 2: gr[k] += v * vs * vs; gsv[k] += v * 2 * rho * vs; break;             // mu
-        case 3: gr[k] += v * vp; gp[k] += v * rho; break;                              // Zp
-        case 4: gr[k] += v * vs; gsv[k] += v * rho; break;                             // Zs
-      }
-    };
+    // chain rule on the device (gathers over face neighbours), then reorder
+    const int mw = 3 + 2 * c->M;
+    std::vector<double> mat((size_t)c->Kp * mw, 0.0);
     for (int64_t k = 0; k < c->K; ++k) {
-      const double* x = &w[(size_t)c->user_to_internal[k] * NG];
-      for (int t = 0; t < 5; ++t) add(k, t, x[t]);
-      const double rho = c->rho[k], vp = c->vp[k], vs = c->vs[k];
-      for (int l = 0; l < c->M; ++l) {   // a_l = rho vp^2 Yp - 2 rho vs^2 Ys, b_l = 2 rho vs^2 Ys
-        const double yp = c->yp[k * c->M + l], ys = c->ys[k * c->M + l];
-        const double ga = x[5 + 2 * l], gb = x[6 + 2 * l];
-        gr[k] += ga * (vp * vp * yp - 2 * vs * vs * ys) + gb * 2 * vs * vs * ys;
-        gp[k] += ga * 2 * rho * vp * yp;
-        gsv[k] += -ga * 4 * rho * vs * ys + gb * 4 * rho * vs * ys;
-      }
-      for (int i = 0; i < 4; ++i) {
-        const int64_t n = c->nbr[k * 4 + i];
-        if (n < 0) continue;
-        add(n, 3, x[11 + 2 * i]);         // the neighbour's impedances in the own flux
-        add(n, 4, x[12 + 2 * i]);
-        const double* y = x + 19 + 7 * i; // the neighbour's flux across this face
-        for (int t = 0; t < 5; ++t) add(n, t, y[t]);
-        add(k, 3, y[5]);
-        add(k, 4, y[6]);
+      double* m = &mat[(size_t)c->user_to_internal[k] * mw];
+      m[0] = c->rho[k];
+      m[1] = c->vp[k];
+      m[2] = c->vs[k];
+      for (int l = 0; l < c->M; ++l) {
+        m[3 + 2 * l] = c->yp[k * c->M + l];
+        m[4 + 2 * l] = c->ys[k * c->M + l];
       }
     }
-    if (g_rho) std::copy(gr.begin(), gr.end(), g_rho);
-    if (g_vp) std::copy(gp.begin(), gp.end(), g_vp);
-    if (g_vs) std::copy(gsv.begin(), gsv.end(), g_vs);
+    if ((rc = dev_reserve(c, c->amat, mat.size() * sizeof(double))) ||
+        (rc = dev_reserve(c, c->agrad, (size_t)c->Kp * 3 * sizeof(double))))
+      return rc;
+    HIPCHK(c, hipMemcpyAsync(c->amat.p, mat.data(), mat.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if ((rc = chk(launch_material_gradient((const double*)c->agacc.p, (const int*)c->FI.p, (const double*)c->amat.p,
+                                           c->M, c->Kp, (double*)c->agrad.p, c->stream),
+                  "material gradient kernel")))
+      return rc;
+    std::vector<double> gi((size_t)c->Kp * 3);
+    HIPCHK(c, hipMemcpyAsync(gi.data(), c->agrad.p, gi.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < c->K; ++k) {
+      const double* x = &gi[(size_t)c->user_to_internal[k] * 3];
+      if (g_rho) g_rho[k] = x[0];
+      if (g_vp) g_vp[k] = x[1];
+      if (g_vs) g_vs[k] = x[2];
+    }
   }
   // back to the final state
   HIPCHK(c, hipMemcpy(c->Qe.p, fin, we * rs, hipMemcpyDeviceToDevice));
