@@ -1463,13 +1463,14 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   if (dj_seis && c->n_rec > 0)
     HIPCHK(c, hipMemcpy(c->aseis.p, dj_seis, (size_t)c->n_rec * c->rec_ns * LPE * sizeof(double),
                         hipMemcpyHostToDevice));
-  // keep the final state: the sweep overwrites the DOFs
-  char* fin = (char*)c->afinal.p;
-  HIPCHK(c, hipMemcpy(fin, c->Qe.p, we * rs, hipMemcpyDeviceToDevice));
-  if (wa) HIPCHK(c, hipMemcpy(fin + we * rs, c->Qa.p, wa * rs, hipMemcpyDeviceToDevice));
+  // the replays run on a state of their own, so the context's DOFs stay
+  // those of the final time
+  char* rep_state = (char*)c->afinal.p;
 
   const AdvanceArgs A = advance_args(c);
-  const KPtrs p = kptrs(c);
+  KPtrs p = kptrs(c);
+  p.Qe = rep_state;
+  p.Qa = rep_state + we * rs;
   APtrs ad;
   ad.Le = c->aLe.p;
   ad.La = c->aLa.p;
@@ -1495,8 +1496,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
     // restore the segment's start and replay it forward, keeping the state
     // at the start of every level's predictions
     const char* ck = (const char*)c->ckpts[si].second.p;
-    HIPCHK(c, hipMemcpyAsync(c->Qe.p, ck, we * rs, hipMemcpyDeviceToDevice, c->stream));
-    if (wa) HIPCHK(c, hipMemcpyAsync(c->Qa.p, ck + we * rs, wa * rs, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(rep_state, ck, (we + wa) * rs, hipMemcpyDeviceToDevice, c->stream));
     const long long clock0 = (long long)L0;
     HIPCHK(c, hipMemcpyAsync(c->dclock.p, &clock0, sizeof clock0, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1511,8 +1511,13 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
         a.kind = KIND_NEIGHBOR;
         if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
       }
-      HIPCHK(c, hipMemcpyAsync(hist_e(j), c->Qe.p, we * rs, hipMemcpyDeviceToDevice, c->stream));
-      if (wa) HIPCHK(c, hipMemcpyAsync(hist_a(j), c->Qa.p, wa * rs, hipMemcpyDeviceToDevice, c->stream));
+      {
+        // only the element groups that predict at this level are read back
+        const size_t groups = (size_t)(a.end + EPW - 1) / EPW;
+        const size_t pe = groups * (we / c->G), pa = wa ? groups * (wa / c->G) : 0;
+        HIPCHK(c, hipMemcpyAsync(hist_e(j), p.Qe, pe * rs, hipMemcpyDeviceToDevice, c->stream));
+        if (wa) HIPCHK(c, hipMemcpyAsync(hist_a(j), p.Qa, pa * rs, hipMemcpyDeviceToDevice, c->stream));
+      }
       a.kind = KIND_PREDICT;
       if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
     }
@@ -1571,9 +1576,6 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
       if (g_vs) g_vs[k] = x[2];
     }
   }
-  // back to the final state
-  HIPCHK(c, hipMemcpy(c->Qe.p, fin, we * rs, hipMemcpyDeviceToDevice));
-  if (wa) HIPCHK(c, hipMemcpy(c->Qa.p, fin + we * rs, wa * rs, hipMemcpyDeviceToDevice));
   const long long clock_end = (long long)L_end;
   HIPCHK(c, hipMemcpy(c->dclock.p, &clock_end, sizeof clock_end, hipMemcpyHostToDevice));
   return EDG_OK;
