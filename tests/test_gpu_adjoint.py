@@ -122,7 +122,7 @@ def test_adjoint_matches_oracle_fp64(order, mech, n_clusters, explicit, every):
     assert np.array_equal(ctx.read_dofs(), qT)
 
 
-@pytest.mark.parametrize("order", [4, 5])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_adjoint_matches_oracle_fp32(order):
     ctx, w = _setup(order, 3, 2, False)
     x, y, sb = _inputs(ctx, 40 + order)
@@ -282,3 +282,27 @@ def test_adjoint_5k_tets_order4(mech):
     assert e_s <= 1e-11
     assert e_q <= TOL64_Q
     assert e_g <= TOL64_G
+
+
+def test_adjoint_call_errors():
+    """No checkpoints, dropped checkpoints and batched contexts are refused
+    with EDG_ESTATE / EDG_EINVAL instead of computing anything."""
+    from paper_2202_10313_amd import Context, EdgError
+    ctx, w = _setup(2, 0, 2, True)
+    with pytest.raises(EdgError, match="EDG_ESTATE"):
+        ctx.adjoint()
+    ctx.set_checkpointing(1)
+    ctx.set_initial(synth.random_state(1, ctx.K, ctx.nq, ctx.B))
+    ctx.advance_to(w["sync"])
+    ctx.upload_materials(w["mat"]["rho"], w["mat"]["vp"], w["mat"]["vs"])    # drops the checkpoints
+    with pytest.raises(EdgError, match="EDG_ESTATE"):
+        ctx.adjoint()
+    with pytest.raises(EdgError, match="EDG_EINVAL"):
+        ctx.set_checkpointing(-1)
+    mesh, mat = _mesh()
+    c2 = Context(2, mechanisms=0, n_clusters=1, fp64=True, n_runs=2)
+    c2.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+    c2.upload_materials(mat["rho"], mat["vp"], mat["vs"])
+    c2.upload_clusters(None)
+    with pytest.raises(EdgError, match="EDG_EINVAL"):
+        c2.set_checkpointing(1)
