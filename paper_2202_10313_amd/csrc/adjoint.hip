@@ -29,18 +29,20 @@
 //    parameters); then runs the Cauchy-Kowalevski recursion backwards and adds
 //    the adjoint of the start-of-step state to Qbar.  It clears the slots it
 //    consumed (B3 after its even step, the first of the pair the coarser
-//    neighbour read as one sum).
+//    neighbour read as one sum).  The transposed update also leaves u in S0,
+//    where the two-wave transposed prediction reads its own flux's part.
 //
 // Material derivatives: every product that involves a material parameter
 // (lam, mu, 1/rho, a_l, b_l, the impedances of the flux solver) adds its
-// adjoint-weighted partial derivative to per-element FP64 words (NG); the
-// host applies the chain rule to rho, vp, vs.
+// adjoint-weighted partial derivative to per-element FP64 words (NG);
+// k_material_gradient applies the chain rule to rho, vp, vs.
 //
-// Work mapping as in the forward k_level: one wave of 64 lanes owns 7
+// Work mapping: k_adjoint as the forward k_level (one wave of 64 lanes owns 7
 // elements, lane 9e + q holds row q of element e for all modes and the memory
-// variables of the modes q + 9 jb; reference-matrix products are the
-// generated straight-line code and its transposes; row-mixing products go
-// through LDS.
+// variables of the modes q + 9 jb); k_adjoint2 (FP32, O = 4, 5, transposed
+// prediction) as the forward k_level2 (two waves per 7 elements, modes split
+// between them).  Reference-matrix products are the generated straight-line
+// code and its transposes; row-mixing products go through LDS.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
