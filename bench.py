@@ -22,6 +22,13 @@ context (one launch per LTS level for all runs), each with its own Ricker
 source (fc uniform in 1-3 Hz, random moment tensor, uniform location in the
 top 5 km), and reports run-element updates per second against the plain
 single-run value.
+
+The "adjoint" entry times the gradient of a receiver misfit with respect to
+rho, vp, vs over a short window: the checkpointed forward plus the reverse
+sweep, against the plain forward of the same cycles.  Its main figure keeps
+the window as one checkpoint segment (the forward records every level's
+state, the sweep replays nothing); "checkpoint_per_cycle" stores one
+checkpoint per cycle instead and replays all but the last.
 """
 from __future__ import annotations
 
@@ -52,7 +59,7 @@ PAPER_FLOPS_ALL_SPARSITY = 212688
 # the cycle's element updates.  Valid only for the kernel sources it was taken
 # on (their SHA-256 below); after any change the roofline reports null.
 TRAFFIC_BYTES_PER_UPDATE = 15327.1
-TRAFFIC_SOURCES_SHA256 = "3ab4ff0b274836aab21e2fe23235f467b8ac734b41578f91c88ffd561a2604ce"
+TRAFFIC_SOURCES_SHA256 = "68ae343c51d0f78a3f62ac34ddc2d9e18d6c0203566337c96ecbef2c32a04cfc"
 KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "device_common.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
 
@@ -205,11 +212,12 @@ def main():
         ctx.close()
         return res
 
-    def measure_adjoint(order, steps):
+    def measure_adjoint(order, steps, every):
         """Gradient of J = 1/2 sum_r,s |seis|^2 dt_sample with respect to rho,
         vp, vs over `steps` LTS cycles: the checkpointed forward (a checkpoint
-        per cycle) plus the reverse sweep (replay of each cycle from its
-        checkpoint, adjoint kernels backwards).  One untimed cycle first."""
+        every `every` cycles; the final segment records its level states) plus
+        the reverse sweep (replay of every other segment from its checkpoint,
+        adjoint kernels backwards).  One untimed cycle first."""
         ctx = Context(order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream)
         ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
         ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
@@ -220,7 +228,7 @@ def main():
         ctx.set_sources(src["xyz"], src["moment"], STF_RICKER, np.array([[2.0, 0.0]]))
         dts = 0.005
         ctx.set_receivers(rec, dts, int((steps + 2) * sync / dts) + 2)
-        ctx.set_checkpointing(1)
+        ctx.set_checkpointing(every)
         out = {}
         for phase, n in (("warm", 1), ("timed", steps)):
             ctx.rewind()
@@ -297,7 +305,11 @@ def main():
     adjoint = None
     if args.adjoint_steps > 0:
         print(f"[bench] forward + adjoint: O={args.order}, {args.adjoint_steps} cycles", file=sys.stderr, flush=True)
-        a = measure_adjoint(args.order, args.adjoint_steps)
+        # one segment over the window (its level states recorded by the
+        # forward, no replay), then a checkpoint per cycle (less memory; every
+        # segment but the last replayed)
+        a = measure_adjoint(args.order, args.adjoint_steps, args.adjoint_steps)
+        a1 = measure_adjoint(args.order, args.adjoint_steps, 1) if args.adjoint_steps > 1 else a
         wall_plain = wall / args.steps * args.adjoint_steps          # plain forward of the same cycles
         av = a["updates"] / (a["fwd"] + a["adj"])
         adjoint = {"value": av, "unit": "elem-updates/s (forward updates per second of forward + gradient)",
@@ -305,7 +317,10 @@ def main():
                    "forward_checkpointed_ms": a["fwd"] * 1e3, "reverse_sweep_ms": a["adj"] * 1e3,
                    "cost_vs_plain_forward": (a["fwd"] + a["adj"]) / wall_plain,
                    "reverse_vs_plain_forward": a["adj"] / wall_plain,
-                   "checkpoint_every_cycles": 1,
+                   "checkpoint_every_cycles": args.adjoint_steps,
+                   "checkpoint_per_cycle": {"forward_checkpointed_ms": a1["fwd"] * 1e3,
+                                            "reverse_sweep_ms": a1["adj"] * 1e3,
+                                            "cost_vs_plain_forward": (a1["fwd"] + a1["adj"]) / wall_plain},
                    "misfit": "1/2 sum |seismogram|^2 dt_sample over the 64 receivers; gradient w.r.t. rho, vp, vs"}
         print(f"[bench] forward + adjoint: {av:.4g} element updates/s, {adjoint['cost_vs_plain_forward']:.2f}x the "
               f"plain forward", file=sys.stderr, flush=True)

@@ -234,7 +234,8 @@ __device__ __forceinline__ void gadd(double* gs, int w, double v) { atomicAdd(gs
 // memory-variable rows in LDS, so it is its own instantiation with a small
 // LDS footprint (more workgroups per CU).
 template <class R, int O, int M, bool UPD>
-__global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(UPD && sizeof(R) == 4 ? 4 : 1)))
+void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
   using RF = edg_gen::Ref<O>;
   using L = AdjLds<R, O, M>;
   constexpr int B = RF::B, F = RF::F, FP = RF::FP;
@@ -328,35 +329,30 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
   if constexpr (UPD) {
     put_weighted();
     __syncthreads();
-    face_adjoints();
     if (!valid) return;
     const int n = step_fin_of(a, cl);
-    {
-      // the own-flux face adjoints of this step, for the two-wave transposed
-      // prediction (the Qbar it reads is unchanged until then)
-      R* const S0 = reinterpret_cast<R*>(ad.S0) + (size_t)elem * sstride;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int f = 0; f < FP; ++f) {
-          S0[(i * ADJ_ROWS + q) * FP + f] = ue[i * FP + f];
-          if (is_stress) S0[(i * ADJ_ROWS + 9 + q) * FP + f] = ua[i * FP + f];
-        }
-    }
+    // The own-flux face adjoints of this step go to S0, for the two-wave
+    // transposed prediction (the Qbar it reads is unchanged until then); the
+    // neighbour-data ones are added to the slot of the buffer read across each
+    // face.  One face and one row kind at a time: pass 0 the elastic row q
+    // from le, pass 1 the omega-weighted memory-variable row 9 + q of the
+    // stress lanes from LDS (few live registers, several waves per SIMD).
+    R* const S0 = reinterpret_cast<R*>(ad.S0) + (size_t)elem * sstride;
     R* const S1 = reinterpret_cast<R*>(ad.S1);
     R* const S2 = reinterpret_cast<R*>(ad.S2);
     R* const S3 = reinterpret_cast<R*>(ad.S3);
+    auto scatter = [&](const R* u, int i, int row) {
+      R* const s0 = S0 + (size_t)(i * ADJ_ROWS + row) * FP;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+      for (int f = 0; f < FP; ++f) s0[f] = u[f];
       const int nb = FI[3 * i];
-      if (nb < 0) continue;
+      if (nb < 0) return;
       const int code = FI[3 * i + 1];
       const size_t aux = (size_t)FI[3 * i + 2];
       const int j = code & 15, rel = ((code >> 8) & 15) - 1;
-      const size_t fo = (size_t)j * ADJ_ROWS * FP;
-      R* d1 = nullptr;
+      const size_t fo = (size_t)(j * ADJ_ROWS + row) * FP;
+      R* d1;
       R* d2 = nullptr;
-      R sgn2 = R(1);
       if (rel == 0) {
         d1 = S1 + (size_t)nb * sstride + fo;
       } else if (rel < 0) {          // finer neighbour: its B3
@@ -366,20 +362,30 @@ __global__ __launch_bounds__(64) void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) 
       } else {                       // coarser neighbour, second half: B1 - B2
         d1 = S1 + (size_t)nb * sstride + fo;
         d2 = S2 + aux * sstride + fo;
-        sgn2 = R(-1);
       }
 #pragma unroll
-      for (int f = 0; f < FP; ++f) {
-        d1[q * FP + f] += ue[i * FP + f];
-        if (is_stress) d1[(9 + q) * FP + f] += ua[i * FP + f];
-      }
-      if (d2) {
+      for (int f = 0; f < FP; ++f) d1[f] += u[f];
+      if (d2)
 #pragma unroll
-        for (int f = 0; f < FP; ++f) {
-          d2[q * FP + f] += sgn2 * ue[i * FP + f];
-          if (is_stress) d2[(9 + q) * FP + f] += sgn2 * ua[i * FP + f];
-        }
-      }
+        for (int f = 0; f < FP; ++f) d2[f] -= u[f];
+    };
+    auto faces = [&](const R* t, int row) {
+      R u[FP];
+      RF::trace_f0(t, u);
+      scatter(u, 0, row);
+      RF::trace_f1(t, u);
+      scatter(u, 1, row);
+      RF::trace_f2(t, u);
+      scatter(u, 2, row);
+      RF::trace_f3(t, u);
+      scatter(u, 3, row);
+    };
+    faces(le, q);
+    if (M > 0 && is_stress) {
+      R wrow[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) wrow[b] = Cx[q * B + b];
+      faces(wrow, 9 + q);
     }
     return;
   }

@@ -105,6 +105,11 @@ struct edg_ctx {
   // advance starts a segment and stores the state at its start
   int ckpt_every = 0;
   std::vector<std::pair<int64_t, DevBuf>> ckpts;    // (level, Qe then Qa of run 0)
+  // ahist holds, for the segment that starts at level hist_L0 and spans
+  // hist_J levels, the state at the start of every level's predictions (the
+  // final segment of a checkpointed advance records it; a replay rewrites it)
+  bool hist_valid = false;
+  int64_t hist_L0 = 0, hist_J = 0;
   // adjoint buffers
   DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal, amat, agrad;
 
@@ -141,6 +146,7 @@ void dev_free(DevBuf& b) {
 void drop_checkpoints(edg_ctx* c) {
   for (auto& ck : c->ckpts) dev_free(ck.second);
   c->ckpts.clear();
+  c->hist_valid = false;
 }
 
 int dev_alloc(edg_ctx* c, DevBuf& b, size_t bytes) {
@@ -1305,6 +1311,72 @@ int store_checkpoint(edg_ctx* c) {
   return 0;
 }
 
+// ahist: one full run-0 state per level of the longest segment (levels
+// 0 .. J-1), of which the element groups that predict at a level are written
+int hist_reserve(edg_ctx* c, int64_t levels) {
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  if (c->ahist.p && c->ahist.bytes >= (size_t)levels * (c->run_qe + c->run_qa) * rs) return 0;
+  c->hist_valid = false;
+  return dev_reserve(c, c->ahist, (size_t)levels * (c->run_qe + c->run_qa) * rs);
+}
+
+// copies the element groups below `end` (those that predict at level j) of
+// the state (Qe, Qa) into level j's record of ahist
+int hist_store(edg_ctx* c, int64_t j, const void* Qe, const void* Qa, int64_t end) {
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  const size_t we = c->run_qe, wa = c->run_qa;
+  char* h = (char*)c->ahist.p + (size_t)j * (we + wa) * rs;
+  const size_t groups = (size_t)(end + EPW - 1) / EPW;
+  HIPCHK(c, hipMemcpyAsync(h, Qe, groups * (we / c->G) * rs, hipMemcpyDeviceToDevice, c->stream));
+  if (wa) HIPCHK(c, hipMemcpyAsync(h + we * rs, Qa, groups * (wa / c->G) * rs, hipMemcpyDeviceToDevice, c->stream));
+  return 0;
+}
+
+// nc >= 1 cycles as one segment whose level states the reverse sweep can use
+// without a replay: every level runs as the neighbour-data update, the copy
+// of the predicting groups' state into ahist, then the prediction (the
+// forward split where the plain advance fuses it), with the level clock held
+// at the segment start and the level offset counted over the segment
+int advance_recorded(edg_ctx* c, int64_t nc) {
+  const int Nc = c->cfg.n_clusters;
+  const int64_t per = (int64_t)1 << (Nc - 1), J = nc * per;
+  int rc = hist_reserve(c, std::max<int64_t>(J, (int64_t)c->ckpt_every * per));
+  if (rc) return rc;
+  c->hist_valid = false;
+  c->ev_used = 0;
+  c->ev_updates.clear();
+  c->ev_launches.clear();
+  const AdvanceArgs A = advance_args(c);
+  auto chk = [&](int e, const char* what) {
+    return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
+  };
+  LevelArgs a = base_args(c);
+  a.run0 = 0;
+  for (int64_t j = 0; j <= J; ++j) {
+    const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
+    a.jrel = (int)j;
+    a.end = c->cl_end[lmax];
+    if (j > 0) {
+      if (c->n_src > 0 && (rc = chk(A.fn.src(A.p, a, A.sa, c->stream), "source kernel"))) return rc;
+      a.kind = KIND_NEIGHBOR;
+      if ((rc = chk(A.fn.level(A.p, a, 1, c->stream), "level kernel"))) return rc;
+    }
+    if (j == J) break;
+    if ((rc = hist_store(c, j, A.p.Qe, A.p.Qa, a.end))) return rc;
+    a.kind = KIND_PREDICT;
+    if ((rc = chk(A.fn.level(A.p, a, 1, c->stream), "level kernel"))) return rc;
+    if (c->n_rec > 0 && (rc = chk(A.fn.rec(A.p, a, A.ra, c->runs, c->stream), "receiver kernel"))) return rc;
+  }
+  if ((rc = chk(launch_tick((long long*)c->dclock.p, J, c->stream), "clock kernel"))) return rc;
+  c->updates += nc * cycle_updates(c);
+  c->hist_L0 = c->level;
+  c->hist_J = J;
+  c->level += J;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->hist_valid = true;
+  return EDG_OK;
+}
+
 }  // namespace
 
 int edg_advance_to(edg_ctx* c, double t) {
@@ -1322,12 +1394,13 @@ int edg_advance_to(edg_ctx* c, double t) {
   const int64_t nc = (int64_t)ncd;
   if (c->ckpt_every <= 0) return advance_cycles(c, nc);
   // checkpointed: segments of at most ckpt_every cycles, each one an advance
-  // of its own that starts from a stored state
+  // of its own that starts from a stored state; the final one records its
+  // level states, so the reverse sweep starts without a replay
   for (int64_t done = 0; done < nc;) {
     const int64_t seg = std::min<int64_t>(c->ckpt_every, nc - done);
     int rc = store_checkpoint(c);
     if (rc) return rc;
-    if ((rc = advance_cycles(c, seg))) return rc;
+    if ((rc = done + seg == nc ? advance_recorded(c, seg) : advance_cycles(c, seg))) return rc;
     done += seg;
   }
   return EDG_OK;
@@ -1451,7 +1524,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
       (rc = dev_reserve(c, c->agacc, (size_t)c->Kp * NG * sizeof(double))) ||
       (rc = dev_reserve(c, c->arecDb, std::max<size_t>(c->run_recd, 1) * rs)) ||
       (rc = dev_reserve(c, c->aseis, std::max<size_t>((size_t)c->n_rec * c->rec_ns * LPE, 1) * sizeof(double))) ||
-      (rc = dev_reserve(c, c->ahist, n_hist * (we + wa) * rs)) || (rc = dev_reserve(c, c->afinal, (we + wa) * rs)))
+      (rc = hist_reserve(c, (int64_t)n_hist)) || (rc = dev_reserve(c, c->afinal, (we + wa) * rs)))
     return rc;
   // the slots and receiver derivatives return to zero at the end of every
   // sweep (each is cleared by its reader); they are cleared here for the
@@ -1483,7 +1556,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   ad.gacc = (double*)c->agacc.p;
   ad.recDb = c->arecDb.p;
   const double* seis_b = (const double*)c->aseis.p;
-  char* hist = (char*)c->ahist.p;
+  char* const hist = (char*)c->ahist.p;
   auto hist_e = [&](int64_t j) { return (void*)(hist + (size_t)j * (we + wa) * rs); };
   auto hist_a = [&](int64_t j) { return (void*)(hist + ((size_t)j * (we + wa) + we) * rs); };
   auto chk = [&](int e, const char* what) {
@@ -1493,33 +1566,34 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
     const int64_t L0 = c->ckpts[si].first;
     const int64_t J = (si + 1 < nck ? c->ckpts[si + 1].first : L_end) - L0;
     if (J <= 0) continue;
-    // restore the segment's start and replay it forward, keeping the state
-    // at the start of every level's predictions
-    const char* ck = (const char*)c->ckpts[si].second.p;
-    HIPCHK(c, hipMemcpyAsync(rep_state, ck, (we + wa) * rs, hipMemcpyDeviceToDevice, c->stream));
     const long long clock0 = (long long)L0;
     HIPCHK(c, hipMemcpyAsync(c->dclock.p, &clock0, sizeof clock0, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     LevelArgs a = base_args(c);
     a.run0 = 0;
-    for (int64_t j = 0; j < J; ++j) {
-      const int lmax = j == 0 ? Nc - 1 : level_lmax(c, j);
-      a.jrel = (int)j;
-      a.end = c->cl_end[lmax];
-      if (j > 0) {
-        if (c->n_src > 0 && (rc = chk(A.fn.src(p, a, A.sa, c->stream), "source kernel"))) return rc;
-        a.kind = KIND_NEIGHBOR;
+    if (!(c->hist_valid && c->hist_L0 == L0 && c->hist_J == J)) {
+      // restore the segment's start and replay it forward, keeping the state
+      // at the start of every level's predictions
+      c->hist_valid = false;
+      const char* ck = (const char*)c->ckpts[si].second.p;
+      HIPCHK(c, hipMemcpyAsync(rep_state, ck, (we + wa) * rs, hipMemcpyDeviceToDevice, c->stream));
+      for (int64_t j = 0; j < J; ++j) {
+        const int lmax = j == 0 ? Nc - 1 : level_lmax(c, j);
+        a.jrel = (int)j;
+        a.end = c->cl_end[lmax];
+        if (j > 0) {
+          if (c->n_src > 0 && (rc = chk(A.fn.src(p, a, A.sa, c->stream), "source kernel"))) return rc;
+          a.kind = KIND_NEIGHBOR;
+          if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
+        }
+        if ((rc = hist_store(c, j, p.Qe, p.Qa, a.end))) return rc;
+        a.kind = KIND_PREDICT;
         if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
       }
-      {
-        // only the element groups that predict at this level are read back
-        const size_t groups = (size_t)(a.end + EPW - 1) / EPW;
-        const size_t pe = groups * (we / c->G), pa = wa ? groups * (wa / c->G) : 0;
-        HIPCHK(c, hipMemcpyAsync(hist_e(j), p.Qe, pe * rs, hipMemcpyDeviceToDevice, c->stream));
-        if (wa) HIPCHK(c, hipMemcpyAsync(hist_a(j), p.Qa, pa * rs, hipMemcpyDeviceToDevice, c->stream));
-      }
-      a.kind = KIND_PREDICT;
-      if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->hist_L0 = L0;
+      c->hist_J = J;
+      c->hist_valid = true;
     }
     // the levels backwards: transposed predictions, then transposed updates
     for (int64_t j = J; j >= 0; --j) {

@@ -161,6 +161,33 @@ def test_checkpoint_interval_does_not_change_the_result():
     assert _grad_err(out[0], out[1]) <= 1e-13
 
 
+def test_recorded_segment_reuse_and_repeated_sweeps():
+    """The final segment of a checkpointed advance records its level states
+    and the sweep skips its replay: a forward split over two advance calls
+    (the first call's record is stale), repeated sweeps after one forward
+    (the first sweep's replays overwrite the record), and one segment over
+    the whole window agree."""
+    ctx, w = _setup(3, 3, 2, True)
+    x, y, sb = _inputs(ctx, 17)
+    s = w["sync"]
+    ctx.set_sources(SRC["xyz"], SRC["moment"], SRC["stf_kind"], SRC["stf_params"])
+    ctx.set_receivers(REC["xyz"], REC["dt_sample"], REC["n_samples"])
+    ctx.set_checkpointing(1)
+    ctx.set_initial(x)
+    ctx.advance_to(2 * s)
+    ctx.advance_to(3 * s)
+    first = ctx.adjoint(dj_dseis=sb, dj_dq=y)
+    again = ctx.adjoint(dj_dseis=sb, dj_dq=y)
+    ctx.rewind()
+    ctx.set_checkpointing(3)
+    ctx.set_initial(x)
+    ctx.advance_to(3 * s)
+    whole = ctx.adjoint(dj_dseis=sb, dj_dq=y)
+    for other in (again, whole):
+        assert parity(first["q0_b"], other["q0_b"]) <= 1e-13
+        assert _grad_err(first, other) <= 1e-13
+
+
 def test_gradient_matches_central_differences_fp64():
     ctx, w = _setup(3, 3, 2, True)
     x, y, sb = _inputs(ctx, 13)
