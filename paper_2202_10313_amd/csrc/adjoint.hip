@@ -227,6 +227,18 @@ struct AdjLds {
   static constexpr int TOTAL = EPW * REGION;
 };
 
+// the element at 32-bit element offset i from a per-workgroup (uniform) base:
+// the address is a scalar base plus a zero-extended 32-bit lane byte offset,
+// so no 64-bit per-lane address stays live (or spills) across the long loops
+template <class T>
+__device__ __forceinline__ T& at(T* base, uint32_t i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (size_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (size_t)(i * (uint32_t)sizeof(T)));
+}
+
 // adds v to the element's gradient word w (LDS, FP64)
 __device__ __forceinline__ void gadd(double* gs, int w, double v) { atomicAdd(gs + w, v); }
 
@@ -936,8 +948,12 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   const int elem = g * EPW + ec;
   const int cl = cluster_of(a, g * EPW);
   const bool valid = act && (elem < a.cl_vend[cl]);
-  const int slot = ec * LPE + q;
+  // lane slot of the element-group layouts; re-declared opaque at the top of
+  // the long loops, so the compiler recomputes addresses there instead of
+  // hoisting (and spilling) one per access
+  int slot = ec * LPE + q;
   const int base = w ? RF::MB1 : 0;
+  int jb0 = (base + q) / LPE;                      // memory-variable block of the lane's first owned mode
   const int nb = w ? NB1 : NB0;
   R* const reg = lds + ec * L::REGION;
   R* const grad = reg;
@@ -949,7 +965,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   const int* FI = p.FI + (size_t)elem * FI_WORDS;
   R* const Le = reinterpret_cast<R*>(ad.Le) + (size_t)g * B * NSLOT;
   R* const La = reinterpret_cast<R*>(ad.La) + (size_t)g * JB * MM * 6 * NSLOT;
-  R* const De = reinterpret_cast<R*>(ad.De) + (size_t)g * O * B * NSLOT;
+  R* const De = reinterpret_cast<R*>(ad.De) + (size_t)g * (O + ADJ_DE_EXTRA) * B * NSLOT;
+  R* const Dt = De + (size_t)O * B * NSLOT;        // time-integral adjoints (Dt elastic Δt, then Δt/2)
   R* const Da = reinterpret_cast<R*>(ad.Da) + (size_t)g * O * JB * MM * 6 * NSLOT;
   const size_t sstride = (size_t)4 * ADJ_ROWS * FP;
 
@@ -1011,18 +1028,19 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     for (int lb = 0; lb < NBX; ++lb) {
       te[lb] = R(0);
       t2[lb] = R(0);
-      if (lb < nb && act) rx[q * BS + base + lb] = Se[(base + lb) * NSLOT + slot];
+      if (lb < nb && act) rx[q * BS + base + lb] = at(Se, (base + lb) * NSLOT + slot);
     }
 #pragma unroll
     for (int jw = 0; jw < JW; ++jw) {
-      const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+      const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
 #pragma unroll
       for (int l = 0; l < MM; ++l)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) dm[jw][l][c] = (M > 0 && lb < nb) ? Sa[((jb * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+        for (int c = 0; c < 6; ++c) dm[jw][l][c] = (M > 0 && lb < nb) ? at(Sa, ((jb * MM + l) * 6 + c) * NSLOT + slot) : R(0);
     }
 #pragma unroll 1
     for (int d = 0; d < O; ++d) {
+      asm volatile("" : "+v"(slot), "+v"(jb0));
       const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
       const bool more = d + 1 < O;
       __syncthreads();
@@ -1035,16 +1053,16 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         if (valid) {
 #pragma unroll
           for (int lb = 0; lb < NBX; ++lb)
-            if (lb < nb) De[((size_t)d * B + base + lb) * NSLOT + slot] = dv[lb];
+            if (lb < nb) at(De, (d * B + base + lb) * NSLOT + slot) = dv[lb];
           if (M > 0)
 #pragma unroll
             for (int jw = 0; jw < JW; ++jw) {
-              const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+              const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
               if (lb < nb)
 #pragma unroll
                 for (int l = 0; l < MM; ++l)
 #pragma unroll
-                  for (int c = 0; c < 6; ++c) Da[((((size_t)d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = dm[jw][l][c];
+                  for (int c = 0; c < 6; ++c) at(Da, (((d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot) = dm[jw][l][c];
             }
         }
       }
@@ -1225,8 +1243,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   // V = -(lam delta div v + mu (d_j v_i + d_i v_j)) (stress), -rho_inv div sigma (velocity), -omega_l eps (memory)
   R le[NBX];
 #pragma unroll
-  for (int lb = 0; lb < NBX; ++lb) le[lb] = lb < nb ? Le[(base + lb) * NSLOT + slot] : R(0);
-  auto la_at = [&](int jb, int l, int c) -> R& { return La[((jb * MM + l) * 6 + c) * NSLOT + slot]; };
+  for (int lb = 0; lb < NBX; ++lb) le[lb] = lb < nb ? at(Le, (base + lb) * NSLOT + slot) : R(0);
+  auto la_at = [&](int jb, int l, int c) -> R& { return at(La, ((jb * MM + l) * 6 + c) * NSLOT + slot); };
   if (act)
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb)
@@ -1277,7 +1295,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   if (M > 0) {
 #pragma unroll
     for (int jw = 0; jw < JW; ++jw) {
-      const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+      const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
       if (lb < nb && act)
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -1330,27 +1348,43 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   __syncthreads();
   if (w == 0) RF::vol_grad_T_p0(gt0, gt1, gt2, G, lte);
   else RF::vol_grad_T_p1(gt0, gt1, gt2, G, lte);
+  // the time-integral adjoints wait in memory (re-read with each
+  // derivative's data), so they hold no registers across the loop below
+  if (act)
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) {
+        at(Dt, (base + lb) * NSLOT + slot) = lte[lb];
+        at(Dt, (B + base + lb) * NSLOT + slot) = lt2[lb];
+      }
   __syncthreads();
 
   // ---------------------------------------------- time kernel backwards
+  // nbe: adjoint of the next elastic derivative (registers); the adjoint of
+  // the next memory-variable derivative is carried in Da: iteration d reads
+  // the forward D_d there, then overwrites it with its adjoint, which
+  // iteration d - 1 reads
   R nbe[NBX];
-  R nbm[JW][MM][6];
 #pragma unroll
   for (int lb = 0; lb < NBX; ++lb) nbe[lb] = R(0);
-#pragma unroll
-  for (int jw = 0; jw < JW; ++jw)
-#pragma unroll
-    for (int l = 0; l < MM; ++l)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) nbm[jw][l][c] = R(0);
+  auto da_at = [&](int d, int jb, int l, int c) -> R& { return at(Da, (((d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot); };
   R* const recDb = reinterpret_cast<R*>(ad.recDb);
 #pragma unroll 1
   for (int d = O - 1; d >= 0; --d) {
+    asm volatile("" : "+v"(slot), "+v"(jb0));
     const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
     const bool more = d + 1 < O;
     R cur[NBX];
+    {
+      R x1[NBX], x2[NBX];
 #pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) cur[lb] = c_d * lte[lb] + h_d * lt2[lb];
+      for (int lb = 0; lb < NBX; ++lb) {
+        x1[lb] = lb < nb ? at(Dt, (base + lb) * NSLOT + slot) : R(0);
+        x2[lb] = lb < nb ? at(Dt, (B + base + lb) * NSLOT + slot) : R(0);
+      }
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) cur[lb] = c_d * x1[lb] + h_d * x2[lb];
+    }
     if (rec_slot >= 0 && valid) {
       R* rd = recDb + (((size_t)rec_slot * O + d) * LPE + q) * B + base;
 #pragma unroll
@@ -1362,7 +1396,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       if (act)
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
-          if (lb < nb) rx[q * BS + base + lb] = De[((size_t)d * B + base + lb) * NSLOT + slot];
+          if (lb < nb) rx[q * BS + base + lb] = at(De, (d * B + base + lb) * NSLOT + slot);
       __syncthreads();
       {
         R full[B];
@@ -1381,13 +1415,13 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       if (M > 0) {
 #pragma unroll
         for (int jw = 0; jw < JW; ++jw) {
-          const int lb = q + LPE * jw, b = base + lb;
+          const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
           if (lb < nb && act)
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
               R v = R(0);
 #pragma unroll
-              for (int l = 0; l < MM; ++l) v += om[l] * nbm[jw][l][c];
+              for (int l = 0; l < MM; ++l) v += om[l] * da_at(d + 1, jb, l, c);
               coup[c * BS + b] = v;
             }
         }
@@ -1400,39 +1434,46 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       __syncthreads();
     }
     if (M > 0) {
-      // the coupling E: cq_d enters the volume term c_d cq_d and the next derivative
+      // the coupling E: cq_d enters the volume term c_d cq_d and the next
+      // derivative.  The global operands of a mode block (forward D_d, the
+      // carried adjoint, Qbar's memory variables) are loaded in one batch.
       if (is_stress && act)
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
-          if (lb < nb) rx[q * BS + base + lb] = c_d * le[lb] + (more ? nbe[lb] : R(0));
+          if (lb < nb) rx[q * BS + base + lb] = c_d * at(Le, (base + lb) * NSLOT + slot) + (more ? nbe[lb] : R(0));
       __syncthreads();
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
-        const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+        const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
         if (lb < nb) {
+          R dmd[MM][6], nxt[MM][6], lav[MM][6];
+#pragma unroll
+          for (int l = 0; l < MM; ++l)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              dmd[l][c] = da_at(d, jb, l, c);
+              nxt[l][c] = more ? da_at(d + 1, jb, l, c) : R(0);
+              lav[l][c] = la_at(jb, l, c);
+            }
           R cqb[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) cqb[c] = rx[c * BS + b];
           const R cqt = cqb[0] + cqb[1] + cqb[2];
 #pragma unroll
           for (int l = 0; l < MM; ++l) {
-            R dmd[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) dmd[c] = Da[((((size_t)d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot];
-            const R tr = dmd[0] + dmd[1] + dmd[2];
+            const R tr = dmd[l][0] + dmd[l][1] + dmd[l][2];
             double ga = -(double)(cqt * tr), gbb = 0.0;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) gbb -= (double)(cqb[c] * dmd[c]);
+            for (int c = 0; c < 6; ++c) gbb -= (double)(cqb[c] * dmd[l][c]);
             if (valid) {
               gadd(gs, 5 + 2 * l, ga);
               gadd(gs, 6 + 2 * l, gbb);
             }
+            if (act)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-              R v = -om[l] * c_d * la_at(jb, l, c) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
-              if (more) v -= om[l] * nbm[jw][l][c];
-              nbm[jw][l][c] = v;
-            }
+              for (int c = 0; c < 6; ++c)
+                da_at(d, jb, l, c) = -om[l] * (c_d * lav[l][c] + nxt[l][c]) - bl[l] * cqb[c] -
+                                     (c < 3 ? al[l] * cqt : R(0));
           }
         }
       }
@@ -1444,16 +1485,16 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   if (valid) {
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb)
-      if (lb < nb) Le[(base + lb) * NSLOT + slot] = le[lb] + nbe[lb];
+      if (lb < nb) at(Le, (base + lb) * NSLOT + slot) += nbe[lb];
     if (M > 0)
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
-        const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+        const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
         if (lb < nb)
 #pragma unroll
           for (int l = 0; l < MM; ++l)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) la_at(jb, l, c) += nbm[jw][l][c];
+            for (int c = 0; c < 6; ++c) la_at(jb, l, c) += da_at(0, jb, l, c);
       }
   }
   __syncthreads();
