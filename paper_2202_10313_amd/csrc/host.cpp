@@ -109,6 +109,10 @@ struct edg_ctx {
   // hist_J levels, the state at the start of every level's predictions (the
   // final segment of a checkpointed advance records it; a replay rewrites it)
   bool hist_valid = false;
+  // the adjoint face slots and receiver derivatives hold zeros (left so by a
+  // completed reverse sweep: each is cleared by its reader)
+  bool adj_clean = false;
+  bool amat_valid = false;           // amat holds the materials of the current upload, internal order
   int64_t hist_L0 = 0, hist_J = 0;
   // adjoint buffers
   DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal, amat, agrad;
@@ -886,6 +890,7 @@ int edg_upload_materials(edg_ctx* c, const double* rho, const double* vp, const 
   }
   c->have_mat = true;
   drop_checkpoints(c);
+  c->amat_valid = false;
   if (c->have_clusters) {  // re-derive operators, keep clusters and state
     if (c->cfg.fp64) {
       std::vector<double> P;
@@ -907,6 +912,7 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   if (!c->have_mesh || !c->have_mat) return fail(c, EDG_ESTATE, "upload mesh and materials first");
   HIPCHK(c, hipSetDevice(c->cfg.device));
   drop_checkpoints(c);
+  c->amat_valid = false;
   const int64_t K = c->K;
   const int Nc = c->cfg.n_clusters, O = c->O;
   std::vector<double> dt(K);
@@ -1514,6 +1520,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   }
   int rc;
   const size_t n_hist = (size_t)jmax;   // levels 0 .. J-1 of the longest segment
+  const void* const slots_before[5] = {c->aS0.p, c->aS1.p, c->aS2.p, c->aS3.p, c->arecDb.p};
   if ((rc = dev_reserve(c, c->aLe, we * rs)) || (rc = dev_reserve(c, c->aLa, std::max<size_t>(wa, 1) * rs)) ||
       (rc = dev_reserve(c, c->aS0, (size_t)c->Kp * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS1, (size_t)c->Kp * slot_words * rs)) ||
@@ -1527,10 +1534,16 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
       (rc = hist_reserve(c, (int64_t)n_hist)) || (rc = dev_reserve(c, c->afinal, (we + wa) * rs)))
     return rc;
   // the slots and receiver derivatives return to zero at the end of every
-  // sweep (each is cleared by its reader); they are cleared here for the
-  // first use and after a failed sweep
-  for (DevBuf* b : {&c->aLe, &c->aLa, &c->aS0, &c->aS1, &c->aS2, &c->aS3, &c->agacc, &c->arecDb, &c->aseis})
-    HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  // sweep (each is cleared by its reader; S0 is written before it is read);
+  // they are cleared here after a (re)allocation and after a failed sweep
+  const void* const slots_now[5] = {c->aS0.p, c->aS1.p, c->aS2.p, c->aS3.p, c->arecDb.p};
+  bool clean = c->adj_clean;
+  for (int i = 0; i < 5; ++i) clean = clean && slots_before[i] == slots_now[i];
+  c->adj_clean = false;
+  for (DevBuf* b : {&c->aLe, &c->aLa, &c->agacc, &c->aseis}) HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  if (!clean)
+    for (DevBuf* b : {&c->aS0, &c->aS1, &c->aS2, &c->aS3, &c->arecDb})
+      HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (dj_q && (rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) return rc;
   if (dj_seis && c->n_rec > 0)
@@ -1620,22 +1633,25 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   if (g_q0 && (rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, g_q0))) return rc;
   if (g_rho || g_vp || g_vs) {
     // chain rule on the device (gathers over face neighbours), then reorder
-    const int mw = 3 + 2 * c->M;
-    std::vector<double> mat((size_t)c->Kp * mw, 0.0);
-    for (int64_t k = 0; k < c->K; ++k) {
-      double* m = &mat[(size_t)c->user_to_internal[k] * mw];
-      m[0] = c->rho[k];
-      m[1] = c->vp[k];
-      m[2] = c->vs[k];
-      for (int l = 0; l < c->M; ++l) {
-        m[3 + 2 * l] = c->yp[k * c->M + l];
-        m[4 + 2 * l] = c->ys[k * c->M + l];
+    // (the material table is uploaded once per material / cluster upload)
+    if (!c->amat_valid) {
+      const int mw = 3 + 2 * c->M;
+      std::vector<double> mat((size_t)c->Kp * mw, 0.0);
+      for (int64_t k = 0; k < c->K; ++k) {
+        double* m = &mat[(size_t)c->user_to_internal[k] * mw];
+        m[0] = c->rho[k];
+        m[1] = c->vp[k];
+        m[2] = c->vs[k];
+        for (int l = 0; l < c->M; ++l) {
+          m[3 + 2 * l] = c->yp[k * c->M + l];
+          m[4 + 2 * l] = c->ys[k * c->M + l];
+        }
       }
+      if ((rc = dev_reserve(c, c->amat, mat.size() * sizeof(double)))) return rc;
+      HIPCHK(c, hipMemcpy(c->amat.p, mat.data(), mat.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->amat_valid = true;
     }
-    if ((rc = dev_reserve(c, c->amat, mat.size() * sizeof(double))) ||
-        (rc = dev_reserve(c, c->agrad, (size_t)c->Kp * 3 * sizeof(double))))
-      return rc;
-    HIPCHK(c, hipMemcpyAsync(c->amat.p, mat.data(), mat.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if ((rc = dev_reserve(c, c->agrad, (size_t)c->Kp * 3 * sizeof(double)))) return rc;
     if ((rc = chk(launch_material_gradient((const double*)c->agacc.p, (const int*)c->FI.p, (const double*)c->amat.p,
                                            c->M, c->Kp, (double*)c->agrad.p, c->stream),
                   "material gradient kernel")))
@@ -1652,6 +1668,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   }
   const long long clock_end = (long long)L_end;
   HIPCHK(c, hipMemcpy(c->dclock.p, &clock_end, sizeof clock_end, hipMemcpyHostToDevice));
+  c->adj_clean = true;
   return EDG_OK;
 }
 
