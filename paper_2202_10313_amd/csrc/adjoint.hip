@@ -1139,6 +1139,13 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   R* const S1 = reinterpret_cast<R*>(ad.S1);
   R* const S2 = reinterpret_cast<R*>(ad.S2);
   R* const S3 = reinterpret_cast<R*>(ad.S3);
+  // the face words of the element (neighbour, code) for all four faces, read
+  // once: the items below select theirs, so their neighbour-parameter loads
+  // do not wait for an index load first
+  int fnb[4], fcode[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { fnb[i] = FI[3 * i]; fcode[i] = FI[3 * i + 1]; }
+  const int slot2 = FI[13], slot3 = FI[14];
   auto face_phase = [&](const bool b2phase, const R* tint, R* acc) {
     if (act)
 #pragma unroll
@@ -1163,23 +1170,63 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       const int t = q + LPE * (w + 2 * rr);
       if (t < 4 * F && act) {
         const int i = t / F, f = t % F;
-        const int code = FI[3 * i + 1];
+        const int code = i == 0 ? fcode[0] : i == 1 ? fcode[1] : i == 2 ? fcode[2] : fcode[3];
+        const int nbr = i == 0 ? fnb[0] : i == 1 ? fnb[1] : i == 2 ? fnb[2] : fnb[3];
         const int bc = (code >> 4) & 15;
-        const int nbr = FI[3 * i];
+        const bool nflux = nbr >= 0 && valid;
+        // every global operand of the item first (one memory latency per item)
+        R u0[15], u1[15], fpv[6], pnv[5], fnv[6];
+        const R* fp = P + 20 + 6 * i;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fpv[k] = fp[k];
+        if (!b2phase) {
+          const R* x = S0 + (size_t)elem * sstride + (size_t)i * ADJ_ROWS * FP + f;
+#pragma unroll
+          for (int k = 0; k < 15; ++k) u0[k] = (M > 0 || k < 9) ? x[k * FP] : R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 15; ++k) u1[k] = R(0);
+        R* const s1 = !nflux ? nullptr : b2phase ? (has_b2 ? S2 + (size_t)slot2 * sstride : nullptr)
+                                                 : S1 + (size_t)elem * sstride;
+        R* const s3 = (nflux && !b2phase && has_b3) ? S3 + (size_t)slot3 * sstride : nullptr;
+        if (s1) {
+          R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
+#pragma unroll
+          for (int k = 0; k < 15; ++k) u1[k] += x[k * FP];
+        }
+        if (s3) {
+          R* x = s3 + (size_t)i * ADJ_ROWS * FP + f;
+#pragma unroll
+          for (int k = 0; k < 15; ++k) u1[k] += x[k * FP];
+        }
+        if (nflux) {
+          const R* Pn = reinterpret_cast<const R*>(p.P) + (size_t)nbr * NPARAM;
+          const R* fn = Pn + 20 + 6 * (code & 15);
+#pragma unroll
+          for (int k = 0; k < 5; ++k) pnv[k] = Pn[9 + k];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) fnv[k] = fn[k];
+        }
+        // the slots read are cleared (B3 only after its even step)
+        if (s1) {
+          R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
+#pragma unroll
+          for (int k = 0; k < 15; ++k) x[k * FP] = R(0);
+        }
+        if (s3 && (nn & 1) == 0) {
+          R* x = s3 + (size_t)i * ADJ_ROWS * FP + f;
+#pragma unroll
+          for (int k = 0; k < 15; ++k) x[k * FP] = R(0);
+        }
         R tr[9], zero9[9], tb[9], ob[9], pb[7];
 #pragma unroll
         for (int k = 0; k < 9; ++k) { tr[k] = pm[(i * LPE + k) * FS + f]; zero9[k] = R(0); tb[k] = R(0); ob[k] = R(0); }
         if (!b2phase) {
           // own flux: the element's trace is the inside state
-          const R* u0 = S0 + (size_t)elem * sstride + (size_t)i * ADJ_ROWS * FP + f;
-          R u[15];
-#pragma unroll
-          for (int k = 0; k < 15; ++k) u[k] = (M > 0 || k < 9) ? u0[k * FP] : R(0);
-          const R* fp = P + 20 + 6 * i;
 #pragma unroll
           for (int k = 0; k < 7; ++k) pb[k] = R(0);
-          const R zpp = bc == 0 ? fp[4] : zp, zsp = bc == 0 ? fp[5] : zs;
-          godunov_adj<R>(u, tr, zero9, fp[0], fp[1], fp[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fp[3], bc, tb, ob, pb);
+          const R zpp = bc == 0 ? fpv[4] : zp, zsp = bc == 0 ? fpv[5] : zs;
+          godunov_adj<R>(u0, tr, zero9, fpv[0], fpv[1], fpv[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fpv[3], bc, tb, ob, pb);
           if (valid) {
             gadd(gs, 0, pb[0]);
             gadd(gs, 1, pb[1]);
@@ -1190,34 +1237,16 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
             gadd(gs, bc == 0 ? 12 + 2 * i : 4, pb[6]);
           }
         }
-        if (nbr >= 0 && valid) {
+        if (nflux) {
           // the neighbour's flux reads this element's buffer: B1 (+ B3) or B2
-          R* s1 = b2phase ? (has_b2 ? S2 + (size_t)FI[13] * sstride : nullptr) : S1 + (size_t)elem * sstride;
-          R* s3 = (!b2phase && has_b3) ? S3 + (size_t)FI[14] * sstride : nullptr;
-          R u[15];
-#pragma unroll
-          for (int k = 0; k < 15; ++k) u[k] = R(0);
-          if (s1) {
-            R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
-#pragma unroll
-            for (int k = 0; k < 15; ++k) { u[k] += x[k * FP]; x[k * FP] = R(0); }
-          }
-          if (s3) {
-            R* x = s3 + (size_t)i * ADJ_ROWS * FP + f;
-            const bool clear3 = (nn & 1) == 0;
-#pragma unroll
-            for (int k = 0; k < 15; ++k) { u[k] += x[k * FP]; if (clear3) x[k * FP] = R(0); }
-          }
           if (M == 0)
 #pragma unroll
-            for (int k = 9; k < 15; ++k) u[k] = R(0);
-          const int j = code & 15;
-          const R* Pn = reinterpret_cast<const R*>(p.P) + (size_t)nbr * NPARAM;
-          const R* fn = Pn + 20 + 6 * j;
+            for (int k = 9; k < 15; ++k) u1[k] = R(0);
 #pragma unroll
           for (int k = 0; k < 7; ++k) pb[k] = R(0);
-          godunov_adj<R>(u, zero9, tr, fn[0], fn[1], fn[2], Pn[12], Pn[13], fn[4], fn[5], Pn[10], Pn[11], Pn[9], fn[3], 0,
-                         ob, tb, pb);
+          // (rho_inv, lam, mu, Zp, Zs) of the neighbour are its words 9..13
+          godunov_adj<R>(u1, zero9, tr, fnv[0], fnv[1], fnv[2], pnv[3], pnv[4], fnv[4], fnv[5], pnv[1], pnv[2], pnv[0],
+                         fnv[3], 0, ob, tb, pb);
 #pragma unroll
           for (int k = 0; k < 7; ++k) gadd(gs, 19 + 7 * i + k, pb[k]);
         }
