@@ -1338,39 +1338,53 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   __syncthreads();
   // gradient-entry adjoints of this row, own modes, into its slots (sign s:
   // -1 for the volume kernel, +1 for the time kernel's next derivative)
+  // Branch-free: every lane forms its three (row, direction) entries as
+  //   A rx[r] + C coup[c] + L (rx[0] + rx[1] + rx[2]):
+  // velocity row i, direction k: (1 + delta_ik) mu sigma_sym(i,k) +
+  //   (M > 0) (1 - delta_ik / 2)... i.e. fa coupling sum of sym(i,k) + delta_ik lam tr(sigma);
+  // stress row (qi, qj), direction k in {qi, qj}: rho_inv v_(other index);
+  // directions a stress row does not use write nothing
   auto write_gb = [&](const R sgn) {
-    if (!act) return;
-    if (!is_stress) {
-      const int i = q - 6;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int sk = sym_index(i, k);
-        const R fm = i == k ? R(2) : R(1), fa = i == k ? R(1) : R(0.5);
-        R* dst = grad + aslot(q, k) * BS;
+    for (int k = 0; k < 3; ++k) {
+      int rrow, crow;
+      R A, C, Lw;
+      bool wr;
+      if (!is_stress) {
+        const int i = q - 6, sk = sym_index(i, k);
+        rrow = sk;
+        crow = sk;
+        A = (i == k ? R(2) : R(1)) * mu;
+        C = i == k ? R(1) : R(0.5);
+        Lw = i == k ? lam : R(0);
+        wr = act;
+      } else {
+        const int iv = k == qj ? qi : (k == qi ? qj : -1);
+        rrow = 6 + (iv < 0 ? 0 : iv);
+        crow = 0;
+        A = rho_inv;
+        C = R(0);
+        Lw = R(0);
+        wr = act && iv >= 0;
+      }
+      // all reads of a direction, then its stores (the stores may alias the
+      // exchange rows for the compiler, so interleaving them would serialise
+      // every read behind the previous store)
+      R v[NBX];
 #pragma unroll
-        for (int lb = 0; lb < NBX; ++lb) {
-          const int b = base + lb;
-          if (lb < nb) {
-            R v = fm * mu * rx[sk * BS + b] + (M > 0 ? fa * coup[sk * BS + b] : R(0));
-            if (i == k) v += lam * (rx[0 * BS + b] + rx[1 * BS + b] + rx[2 * BS + b]);
-            dst[b] = sgn * v;
-          }
+      for (int lb = 0; lb < NBX; ++lb) {
+        const int b = base + lb;
+        v[lb] = R(0);
+        if (lb < nb) {
+          v[lb] = A * rx[rrow * BS + b] + Lw * (rx[b] + rx[BS + b] + rx[2 * BS + b]);
+          if (M > 0) v[lb] += C * coup[crow * BS + b];
         }
       }
-    } else {
+      R* const dst = grad + aslot(q, k) * BS;
+      if (wr)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        int iv = -1;
-        if (k == qj) iv = qi;
-        else if (k == qi) iv = qj;
-        if (iv < 0) continue;
-        R* dst = grad + aslot(q, k) * BS;
-#pragma unroll
-        for (int lb = 0; lb < NBX; ++lb) {
-          const int b = base + lb;
-          if (lb < nb) dst[b] = sgn * rho_inv * rx[(6 + iv) * BS + b];
-        }
-      }
+        for (int lb = 0; lb < NBX; ++lb)
+          if (lb < nb) dst[base + lb] = sgn * v[lb];
     }
   };
   write_gb(R(-1));
