@@ -1455,20 +1455,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
           if (lb < nb) rx[q * BS + base + lb] = nbe[lb];
-      if (M > 0) {
-#pragma unroll
-        for (int jw = 0; jw < JW; ++jw) {
-          const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
-          if (lb < nb && act)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-              R v = R(0);
-#pragma unroll
-              for (int l = 0; l < MM; ++l) v += om[l] * da_at(d + 1, jb, l, c);
-              coup[c * BS + b] = v;
-            }
-        }
-      }
+      // (coup holds the omega-weighted sums of the next memory-variable
+      // adjoint, written by the coupling block of the step before)
       __syncthreads();
       write_gb(R(1));
       __syncthreads();
@@ -1502,6 +1490,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) cqb[c] = rx[c * BS + b];
           const R cqt = cqb[0] + cqb[1] + cqb[2];
+          R ws[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
           for (int l = 0; l < MM; ++l) {
             const R tr = dmd[l][0] + dmd[l][1] + dmd[l][2];
@@ -1512,12 +1501,18 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
               gadd(gs, 5 + 2 * l, ga);
               gadd(gs, 6 + 2 * l, gbb);
             }
-            if (act)
 #pragma unroll
-              for (int c = 0; c < 6; ++c)
-                da_at(d, jb, l, c) = -om[l] * (c_d * lav[l][c] + nxt[l][c]) - bl[l] * cqb[c] -
-                                     (c < 3 ? al[l] * cqt : R(0));
+            for (int c = 0; c < 6; ++c) {
+              const R v = -om[l] * (c_d * lav[l][c] + nxt[l][c]) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
+              if (act) da_at(d, jb, l, c) = v;
+              ws[c] += om[l] * v;
+            }
           }
+          // the coupling term of the next (lower) derivative's adjoint: coup
+          // is not touched again before the next step reads it
+          if (act)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) coup[c * BS + b] = ws[c];
         }
       }
       __syncthreads();
