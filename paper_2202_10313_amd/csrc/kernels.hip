@@ -806,15 +806,27 @@ void k_level2(KPtrs p, LevelArgs a) {
       }
       __syncthreads();
     }
+    // reads of three modes, then their stores of the next derivative (a store
+    // into the row exchange between reads would, for the compiler, possibly
+    // alias the next mode's reads and put an LDS wait behind every mode)
+    constexpr int CH = 3;
 #pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) {
-      const int b = base + lb;
-      if (lb < nb) {
-        const R cq = M > 0 ? wc * coup[cs + b] : R(0);
-        if (M > 0) qe[lb] += c_d * cq;
-        if (more)
-          rx[q * BS + b] = wabc * (grad[sa + b] + grad[sb + b] + grad[sc + b]) + wde * (grad[sd + b] + grad[se + b]) + cq;
+    for (int l0 = 0; l0 < NBX; l0 += CH) {
+      R nx[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int lb = l0 + k, b = base + lb;
+        nx[k] = R(0);
+        if (lb < NBX && lb < nb) {
+          const R cq = M > 0 ? wc * coup[cs + b] : R(0);
+          if (M > 0) qe[lb] += c_d * cq;
+          nx[k] = wabc * (grad[sa + b] + grad[sb + b] + grad[sc + b]) + wde * (grad[sd + b] + grad[se + b]) + cq;
+        }
       }
+      if (more)
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          if (l0 + k < NBX && l0 + k < nb) rx[q * BS + base + l0 + k] = nx[k];
     }
   }
   // (the barrier after the last loop's products orders every read of RX
