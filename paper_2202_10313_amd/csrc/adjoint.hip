@@ -898,6 +898,16 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
 // direction) pairs the star products use); the face data of the element's
 // own flux come from S0 (written by the transposed update of the same step),
 // so no face adjoint is formed here.
+//
+// The kernel is bound by memory latency at two waves per SIMD, so its state
+// is arranged for few dependent round trips: addresses are a scalar base plus
+// a 32-bit lane offset recomputed in the loops (no hoisted per-lane 64-bit
+// addresses to spill); the time-integral adjoints wait in De's two extra rows
+// and the memory-variable adjoint of the next derivative in Da (overwriting
+// the forward derivative once it is consumed); each face item and each mode
+// block of the coupling issue all their global loads before using any; the
+// coupling block leaves the omega-weighted sums the next step needs in the LDS
+// coupling rows; LDS reads that feed LDS stores are all issued before them.
 template <class R, int O, int M>
 struct AdjLds2 {
   using RF = edg_gen::Ref<O>;
@@ -1340,10 +1350,11 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   // -1 for the volume kernel, +1 for the time kernel's next derivative)
   // Branch-free: every lane forms its three (row, direction) entries as
   //   A rx[r] + C coup[c] + L (rx[0] + rx[1] + rx[2]):
-  // velocity row i, direction k: (1 + delta_ik) mu sigma_sym(i,k) +
-  //   (M > 0) (1 - delta_ik / 2)... i.e. fa coupling sum of sym(i,k) + delta_ik lam tr(sigma);
-  // stress row (qi, qj), direction k in {qi, qj}: rho_inv v_(other index);
-  // directions a stress row does not use write nothing
+  // velocity row i, direction k: A = (1 + delta_ik) mu on exchange row
+  //   sym(i, k), C = 1 (i = k) or 1/2 on coupling row sym(i, k) (anelastic
+  //   only), L = delta_ik lam on the normal-stress rows;
+  // stress row (qi, qj), direction k in {qi, qj}: A = rho_inv on the velocity
+  //   row of the other index; directions a stress row does not use write nothing
   auto write_gb = [&](const R sgn) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
