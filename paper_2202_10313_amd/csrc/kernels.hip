@@ -571,24 +571,28 @@ void k_level2(KPtrs p, LevelArgs a) {
   }
   const int cs = (is_stress ? q : 0) * BS;     // coupling row read by this lane
 
+  // The element state (elastic rows and the memory variables of the owned
+  // modes) is loaded so that its latency overlaps the surface phase: after
+  // the face-trace gathers are issued when there is one (they head the
+  // critical path: face words, then the traces they point to), else here.
   R qe[NBX];
-#pragma unroll
-  for (int lb = 0; lb < NBX; ++lb)
-    qe[lb] = lb < nb ? Qg[(base + lb) * NSLOT + slot] : R(0);
-
-  // memory variables of the owned modes, loaded early so that their latency
-  // overlaps the surface phase
   R qa[JW][MM][6];
+  auto load_state = [&]() {
 #pragma unroll
-  for (int jw = 0; jw < JW; ++jw) {
-    const int lb = q + LPE * jw, b = base + lb;
-    const int jb = b / LPE;
+    for (int lb = 0; lb < NBX; ++lb)
+      qe[lb] = lb < nb ? Qg[(base + lb) * NSLOT + slot] : R(0);
 #pragma unroll
-    for (int l = 0; l < MM; ++l)
+    for (int jw = 0; jw < JW; ++jw) {
+      const int lb = q + LPE * jw, b = base + lb;
+      const int jb = b / LPE;
 #pragma unroll
-      for (int c = 0; c < 6; ++c)
-        qa[jw][l][c] = (M > 0 && lb < nb) ? Qag[((jb * MM + l) * 6 + c) * NSLOT + slot] : R(0);
-  }
+      for (int l = 0; l < MM; ++l)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+          qa[jw][l][c] = (M > 0 && lb < nb) ? Qag[((jb * MM + l) * 6 + c) * NSLOT + slot] : R(0);
+    }
+  };
+  if constexpr (KIND == KIND_PREDICT) load_state();
 
   // ------------------------------------------------ surface: finish step n
   bool coup_pending = false;
@@ -636,6 +640,7 @@ void k_level2(KPtrs p, LevelArgs a) {
         for (int f = 0; f < FP; ++f) dpl[f] = R(0);
       }
     }
+    load_state();
     __syncthreads();
 #pragma unroll 2
     for (int rr = 0; rr < (4 * F + 2 * LPE - 1) / (2 * LPE); ++rr) {
