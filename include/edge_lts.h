@@ -211,8 +211,12 @@ int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cy
 /* every_cycles > 0: from now on edg_advance_to splits its cycles into
  * segments of at most every_cycles cycles and stores the state (device
  * memory, K x Nq x B words each) at the start of every segment; 0 turns it
- * off.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a negative
- * interval.  The checkpoints are dropped again by edg_set_initial,
+ * off.  The final segment of each edg_advance_to call also records the state
+ * at the start of every level's predictions ((levels per segment) x K x Nq x
+ * B words of device memory, reused by edg_adjoint), running its levels split
+ * and without graph replay; its launches are not counted by the timing
+ * queries.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a
+ * negative interval.  The checkpoints are dropped again by edg_set_initial,
  * edg_set_dofs_subset, edg_upload_materials, edg_upload_clusters,
  * edg_set_sources and edg_rewind. */
 int edg_set_checkpointing(edg_ctx* ctx, int32_t every_cycles);
@@ -229,10 +233,12 @@ int edg_rewind(edg_ctx* ctx);
  * NULL = 0), and with respect to the current DOFs, dj_dq [K][Nq][B] (caller
  * order; NULL = 0), writes dJ/d(DOFs at the first checkpoint) to g_q0
  * [K][Nq][B] and dJ/d rho, dJ/d vp, dJ/d vs [K] to g_rho, g_vp, g_vs (any may
- * be NULL).  Each segment is replayed forward from its checkpoint (the states
- * at the start of every level are kept in device memory, (levels per
- * segment) x K x Nq x B words), then its levels run backwards through the
- * adjoint kernels.  All host arrays are caller-owned and only read or written
+ * be NULL).  Segments run backwards; each needs the states at the start of
+ * every level ((levels per segment) x K x Nq x B words of device memory):
+ * the segment the last edg_advance_to call recorded uses them as they are,
+ * every other one is first replayed forward from its checkpoint.  Then its
+ * levels run backwards through the adjoint kernels.  A checkpoint interval
+ * that covers the whole advance therefore needs no replay at all.  All host arrays are caller-owned and only read or written
  * during the call; the DOFs and the time are those of before the call when it
  * returns.  EDG_ESTATE without checkpoints or for n_runs > 1. */
 int edg_adjoint(edg_ctx* ctx, const double* dj_dseis, const double* dj_dq, double* g_q0, double* g_rho,

@@ -44,7 +44,9 @@ class Simulation:
     omega, yp, ys: anelastic inputs (None for an elastic context); q0: initial
     DOFs [K][Nq][B] (None = at rest); t_end: simulated time of every forward
     solve (a multiple of the coarsest step); checkpoint_every: cycles per
-    checkpoint segment of the forward."""
+    checkpoint segment of the forward (the final segment records its level
+    states and is not replayed by the backward, so an interval that covers
+    t_end needs no replay, at (levels per segment) states of device memory)."""
 
     def __init__(self, context, t_end, omega=None, yp=None, ys=None, q0=None, checkpoint_every=1):
         self.context = context
