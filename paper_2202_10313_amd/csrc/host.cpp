@@ -1326,15 +1326,35 @@ int hist_reserve(edg_ctx* c, int64_t levels) {
   return dev_reserve(c, c->ahist, (size_t)levels * (c->run_qe + c->run_qa) * rs);
 }
 
-// copies the element groups below `end` (those that predict at level j) of
-// the state (Qe, Qa) into level j's record of ahist
-int hist_store(edg_ctx* c, int64_t j, const void* Qe, const void* Qa, int64_t end) {
+// The J levels of a segment from a synchronisation point, on the state p:
+// a predict-only launch, fused finish + predict launches, a finish-only
+// launch, each predicting launch also writing the state at the start of its
+// predictions into level j's record of ahist.  The context's own advance
+// (own = true) also samples the receivers and finishes the last steps; a
+// replay stops after the last prediction (the finish is not needed).
+int run_recorded_levels(edg_ctx* c, const AdvanceArgs& A, const KPtrs& p, int64_t J, bool own) {
+  const int Nc = c->cfg.n_clusters;
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
   const size_t we = c->run_qe, wa = c->run_qa;
-  char* h = (char*)c->ahist.p + (size_t)j * (we + wa) * rs;
-  const size_t groups = (size_t)(end + EPW - 1) / EPW;
-  HIPCHK(c, hipMemcpyAsync(h, Qe, groups * (we / c->G) * rs, hipMemcpyDeviceToDevice, c->stream));
-  if (wa) HIPCHK(c, hipMemcpyAsync(h + we * rs, Qa, groups * (wa / c->G) * rs, hipMemcpyDeviceToDevice, c->stream));
+  char* const hist = (char*)c->ahist.p;
+  auto chk = [&](int e, const char* what) {
+    return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
+  };
+  int rc;
+  LevelArgs a = base_args(c);
+  a.run0 = 0;
+  for (int64_t j = 0; j <= (own ? J : J - 1); ++j) {
+    const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
+    a.jrel = (int)j;
+    a.end = c->cl_end[lmax];
+    if (j > 0 && c->n_src > 0 && (rc = chk(A.fn.src(p, a, A.sa, c->stream), "source kernel"))) return rc;
+    a.kind = j == 0 ? KIND_PREDICT : (j == J ? KIND_NEIGHBOR : KIND_FUSED);
+    a.rec_e = j < J ? (void*)(hist + (size_t)j * (we + wa) * rs) : nullptr;
+    a.rec_a = (j < J && wa) ? (void*)(hist + ((size_t)j * (we + wa) + we) * rs) : nullptr;
+    if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
+    if (own && j < J && c->n_rec > 0 && (rc = chk(A.fn.rec(p, a, A.ra, c->runs, c->stream), "receiver kernel")))
+      return rc;
+  }
   return 0;
 }
 
@@ -1356,23 +1376,7 @@ int advance_recorded(edg_ctx* c, int64_t nc) {
   auto chk = [&](int e, const char* what) {
     return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
   };
-  LevelArgs a = base_args(c);
-  a.run0 = 0;
-  for (int64_t j = 0; j <= J; ++j) {
-    const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
-    a.jrel = (int)j;
-    a.end = c->cl_end[lmax];
-    if (j > 0) {
-      if (c->n_src > 0 && (rc = chk(A.fn.src(A.p, a, A.sa, c->stream), "source kernel"))) return rc;
-      a.kind = KIND_NEIGHBOR;
-      if ((rc = chk(A.fn.level(A.p, a, 1, c->stream), "level kernel"))) return rc;
-    }
-    if (j == J) break;
-    if ((rc = hist_store(c, j, A.p.Qe, A.p.Qa, a.end))) return rc;
-    a.kind = KIND_PREDICT;
-    if ((rc = chk(A.fn.level(A.p, a, 1, c->stream), "level kernel"))) return rc;
-    if (c->n_rec > 0 && (rc = chk(A.fn.rec(A.p, a, A.ra, c->runs, c->stream), "receiver kernel"))) return rc;
-  }
+  if ((rc = run_recorded_levels(c, A, A.p, J, true))) return rc;
   if ((rc = chk(launch_tick((long long*)c->dclock.p, J, c->stream), "clock kernel"))) return rc;
   c->updates += nc * cycle_updates(c);
   c->hist_L0 = c->level;
@@ -1590,19 +1594,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
       c->hist_valid = false;
       const char* ck = (const char*)c->ckpts[si].second.p;
       HIPCHK(c, hipMemcpyAsync(rep_state, ck, (we + wa) * rs, hipMemcpyDeviceToDevice, c->stream));
-      for (int64_t j = 0; j < J; ++j) {
-        const int lmax = j == 0 ? Nc - 1 : level_lmax(c, j);
-        a.jrel = (int)j;
-        a.end = c->cl_end[lmax];
-        if (j > 0) {
-          if (c->n_src > 0 && (rc = chk(A.fn.src(p, a, A.sa, c->stream), "source kernel"))) return rc;
-          a.kind = KIND_NEIGHBOR;
-          if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
-        }
-        if ((rc = hist_store(c, j, p.Qe, p.Qa, a.end))) return rc;
-        a.kind = KIND_PREDICT;
-        if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
-      }
+      if ((rc = run_recorded_levels(c, A, p, J, false))) return rc;
       HIPCHK(c, hipStreamSynchronize(c->stream));
       c->hist_L0 = L0;
       c->hist_J = J;

@@ -258,6 +258,24 @@ void k_level(KPtrs p, LevelArgs a) {
     return;
   }
 
+  // the start-of-step state, recorded for the reverse sweep when asked
+  // (every element slot of the group; padding slots get the zeros their state holds)
+  if (a.rec_e != nullptr && e < EPW) {
+    R* const Re = reinterpret_cast<R*>(a.rec_e);
+#pragma unroll
+    for (int b = 0; b < B; ++b) Re[(gbase + b) * NSLOT + slot] = valid ? qe[b] : R(0);
+    if (M > 0) {
+      R* const Ra = reinterpret_cast<R*>(a.rec_a);
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c)
+            Ra[((((size_t)g * JB + jb) * MM + l) * 6 + c) * NSLOT + slot] = valid ? qa[jb][l][c] : R(0);
+    }
+  }
+
   // ------------------------------------------------ time kernel: predict step nn
   const int nn = step_new_of(a, cl);
   const int eflags = FI[12];
@@ -724,6 +742,27 @@ void k_level2(KPtrs p, LevelArgs a) {
         }
     }
     return;
+  }
+
+  // the start-of-step state, recorded for the reverse sweep when asked
+  // (every element slot of the group; padding slots get the zeros their state holds)
+  if (a.rec_e != nullptr && e < EPW) {
+    R* const Re = reinterpret_cast<R*>(a.rec_e) + (size_t)g * B * NSLOT;
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) Re[(base + lb) * NSLOT + slot] = valid ? qe[lb] : R(0);
+    if (M > 0) {
+      R* const Ra = reinterpret_cast<R*>(a.rec_a) + (size_t)g * JB * MM * 6 * NSLOT;
+#pragma unroll
+      for (int jw = 0; jw < JW; ++jw) {
+        const int lb = q + LPE * jw, b = base + lb, jb = b / LPE;
+        if (lb < nb)
+#pragma unroll
+          for (int l = 0; l < MM; ++l)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) Ra[((jb * MM + l) * 6 + c) * NSLOT + slot] = valid ? qa[jw][l][c] : R(0);
+      }
+    }
   }
 
   // ------------------------------------------------ time kernel: predict step nn

@@ -62,6 +62,11 @@ struct LevelArgs {
   double tc[MAX_CLUSTERS][MAX_ORDER];  // dt^{d+1}/(d+1)!
   double th[MAX_CLUSTERS][MAX_ORDER];  // (dt/2)^{d+1}/(d+1)!
   double omega[MAX_MECH];
+  // record for the reverse sweep (null on the plain path): the state at the
+  // start of this level's predictions of the predicting element groups, in
+  // the Qe / Qa layout of run 0 (single-run contexts only)
+  void* rec_e;
+  void* rec_a;
 };
 
 struct SrcArgs {
