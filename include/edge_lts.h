@@ -213,8 +213,8 @@ int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cy
  * memory, K x Nq x B words each) at the start of every segment; 0 turns it
  * off.  The final segment of each edg_advance_to call also records the state
  * at the start of every level's predictions ((levels per segment) x K x Nq x
- * B words of device memory, reused by edg_adjoint), running its levels split
- * and without graph replay; its launches are not counted by the timing
+ * B words of device memory, reused by edg_adjoint; the forward kernels write
+ * it), without graph replay; its launches are not counted by the timing
  * queries.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a
  * negative interval.  The checkpoints are dropped again by edg_set_initial,
  * edg_set_dofs_subset, edg_upload_materials, edg_upload_clusters,
