@@ -1150,6 +1150,8 @@ int edg_set_receivers(edg_ctx* c, int64_t n, const double* xyz, double dt_sample
   return EDG_OK;
 }
 
+}  // extern "C" (the C++ helpers below have C++ linkage)
+
 namespace {
 
 struct AdvanceArgs {
@@ -1388,6 +1390,8 @@ int advance_recorded(edg_ctx* c, int64_t nc) {
 }
 
 }  // namespace
+
+extern "C" {
 
 int edg_advance_to(edg_ctx* c, double t) {
   if (!c) return EDG_EINVAL;
