@@ -188,6 +188,26 @@ def test_recorded_segment_reuse_and_repeated_sweeps():
         assert _grad_err(first, other) <= 1e-13
 
 
+@pytest.mark.parametrize("order,fp64", [(3, True), (3, False), (5, False)])
+def test_recording_leaves_the_forward_unchanged(order, fp64):
+    """A checkpointed advance (its final segment writes the reverse sweep's
+    record from the forward kernels) gives the same DOFs and seismograms,
+    bit for bit, as the plain advance."""
+    out = []
+    for every in (0, 3):
+        ctx, w = _setup(order, 3, 2, fp64)
+        x, y, sb = _inputs(ctx, 23)
+        ctx.set_sources(SRC["xyz"], SRC["moment"], SRC["stf_kind"], SRC["stf_params"])
+        ctx.set_receivers(REC["xyz"], REC["dt_sample"], REC["n_samples"])
+        ctx.set_checkpointing(every)
+        ctx.set_initial(x)
+        ctx.advance_to(3 * w["sync"])
+        out.append((ctx.read_dofs(), ctx.read_receivers()))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_material_upload_between_sweeps():
     """A sweep, a material upload, then another sweep: the second gradient is
     that of the new model (the chain-rule table kept on the device between
