@@ -1174,7 +1174,10 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
           for (int f = 0; f < FP; ++f) pm[((2 * w + ii) * LPE + q) * FS + f] = pt[ii * FP + f];
     }
     __syncthreads();
-    // items (face i, mode f), spread over both waves' lanes of the element
+    // items (face i, mode f), spread over both waves' lanes of the element;
+    // the own flux's element-wide words (1/rho, lam, mu, Zp, Zs) are summed
+    // per lane over the items and added once
+    double own5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int rr = 0; rr < (4 * F + 2 * LPE - 1) / (2 * LPE); ++rr) {
       const int t = q + LPE * (w + 2 * rr);
@@ -1237,12 +1240,9 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
           for (int k = 0; k < 7; ++k) pb[k] = R(0);
           const R zpp = bc == 0 ? fpv[4] : zp, zsp = bc == 0 ? fpv[5] : zs;
           godunov_adj<R>(u0, tr, zero9, fpv[0], fpv[1], fpv[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fpv[3], bc, tb, ob, pb);
+#pragma unroll
+          for (int k = 0; k < 5; ++k) own5[k] += pb[k];
           if (valid) {
-            gadd(gs, 0, pb[0]);
-            gadd(gs, 1, pb[1]);
-            gadd(gs, 2, pb[2]);
-            gadd(gs, 3, pb[3]);
-            gadd(gs, 4, pb[4]);
             gadd(gs, bc == 0 ? 11 + 2 * i : 3, pb[5]);
             gadd(gs, bc == 0 ? 12 + 2 * i : 4, pb[6]);
           }
@@ -1264,6 +1264,9 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         for (int k = 0; k < 9; ++k) pm[(i * LPE + k) * FS + f] = tb[k];
       }
     }
+    if (!b2phase && valid)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) gadd(gs, k, own5[k]);
     __syncthreads();
     {
       R pf[4 * FP];
