@@ -1487,6 +1487,10 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         for (int lb = 0; lb < NBX; ++lb)
           if (lb < nb) rx[q * BS + base + lb] = c_d * at(Le, (base + lb) * NSLOT + slot) + (more ? nbe[lb] : R(0));
       __syncthreads();
+      // the anelastic-weight words of both mode blocks, added once per step
+      double gab[2 * MM];
+#pragma unroll
+      for (int k = 0; k < 2 * MM; ++k) gab[k] = 0.0;
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
         const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
@@ -1511,10 +1515,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
             double ga = -(double)(cqt * tr), gbb = 0.0;
 #pragma unroll
             for (int c = 0; c < 6; ++c) gbb -= (double)(cqb[c] * dmd[l][c]);
-            if (valid) {
-              gadd(gs, 5 + 2 * l, ga);
-              gadd(gs, 6 + 2 * l, gbb);
-            }
+            gab[2 * l] += ga;
+            gab[2 * l + 1] += gbb;
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
               const R v = -om[l] * (c_d * lav[l][c] + nxt[l][c]) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
@@ -1529,6 +1531,9 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
             for (int c = 0; c < 6; ++c) coup[c * BS + b] = ws[c];
         }
       }
+      if (valid)
+#pragma unroll
+        for (int k = 0; k < 2 * MM; ++k) gadd(gs, 5 + k, gab[k]);
       __syncthreads();
     }
 #pragma unroll
