@@ -200,8 +200,8 @@ int edg_get_plan(const edg_ctx* ctx, edg_plan* plan);
 int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cycle);
 
 /* ---- discrete adjoint -------------------------------------------------------
- * The paper names full-waveform inversion as a use of the solver (Sec. I
- * (Introduction)) without an adjoint; these calls give the exact transpose of
+ * The paper names inversion for seismic velocities as a use of such solvers
+ * (Sec. II (Related Work)) without an adjoint; these calls give the exact transpose of
  * the discrete LTS scheme of Sec. III-A (Discrete Formulation) and Sec. V-B
  * (Buffers and Algorithm) as this library computes it, for gradients of
  * receiver misfits with respect to per-element rho, vp and vs.  Time steps,

@@ -2,8 +2,8 @@
 receiver misfit with respect to per-element rho, vp and vs (test
 infrastructure: CPU oracle, FP64).
 
-The paper names full-waveform inversion as a use of the solver (Sec. I
-(Introduction)) but gives no adjoint; this module is a reading written for the
+The paper names inversion for seismic velocities as a use of such solvers
+(Sec. II (Related Work)) but gives no adjoint; this module is a reading written for the
 adjoint kernels.  It is the exact transpose of the discrete scheme that
 solver.Oracle computes -- time kernel, volume and surface kernels, the LTS
 buffers B1/B2/B3 and their consumption rules (Sec. III-A (Discrete

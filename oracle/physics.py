@@ -35,7 +35,13 @@ Pins (tests/test_oracle_physics.py): eigenvalues {+-vp, +-vs x2, 0 x3}; the
 homogeneous flux equals 1/2 A_n (q- + q+) + 1/2 |A_n| (q- - q+) with
 |A_n| = R |Lambda| R^-1; normal-incidence reflection (Z2-Z1)/(Z2+Z1); zero
 traction at the free surface; absorbing flux equals the Godunov flux against a
-zero ghost state.
+zero ghost state.  The anelastic rows of the Jacobians and the coupling E are
+pinned by the viscoelastic dispersion relation: the complex wavenumbers of
+plane waves of q_t + A_n q_x = E q give, on the P and both S branches, the
+fitted constant-Q law of a generalised Maxwell body (1/Q = Im k^2 / Re k^2
+within the fit's +-5% of Qp, Qs over the band), the unrelaxed speeds at high
+frequency and the relaxed ones, M_u (1 - sum_l Y_l), at low frequency; a
+halved shear weight or unsymmetrised memory rows fail it.
 """
 from __future__ import annotations
 

@@ -1,7 +1,7 @@
 // HIP kernels (gfx950) of the discrete adjoint of the clustered rate-2 LTS
 // ADER-DG update: the exact transpose of the forward kernels' arithmetic, for
 // gradients of receiver misfits with respect to the materials.  The paper
-// names inversion as a use (Sec. I (Introduction)) but gives no adjoint; the
+// names inversion as a use (Sec. II (Related Work)) but gives no adjoint; the
 // forward scheme it transposes is that of Sec. III-A (Discrete Formulation)
 // and Sec. V-B (Buffers and Algorithm).
 //

@@ -20,14 +20,21 @@ def parity(a, b):
     """Max over quantities of ||a_q - b_q|| / ||b_group(q)|| (relative L2 over
     all elements and modes; a quantity is measured against the norm of its
     group -- stresses, velocities, one mechanism's memory variables -- so that
-    quantities that vanish do not divide by zero)."""
+    quantities that vanish do not divide by zero), and per element: the max
+    over elements k and groups g of ||a_kg - b_kg|| / max(||b_kg||, rms_g),
+    rms_g = ||b_g|| / sqrt(K), so that one wrong element of a large mesh is
+    not diluted by the others."""
     worst = 0.0
+    K = a.shape[0]
     for (g0, g1) in groups(a.shape[1]):
         den = np.linalg.norm(b[:, g0:g1])
         if den == 0:
             den = 1.0
         for q in range(g0, g1):
             worst = max(worst, np.linalg.norm(a[:, q] - b[:, q]) / den)
+        ek = np.sqrt(np.sum((a[:, g0:g1] - b[:, g0:g1]) ** 2, axis=tuple(range(1, a.ndim))))
+        bk = np.sqrt(np.sum(b[:, g0:g1] ** 2, axis=tuple(range(1, b.ndim))))
+        worst = max(worst, float(np.max(ek / np.maximum(bk, den / math.sqrt(K)))))
     return worst
 
 

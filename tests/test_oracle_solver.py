@@ -17,10 +17,11 @@ def rel_err(a, b):
     measured against the largest quantity of the same kind)."""
     num = ((a - b) ** 2).sum(axis=(0, 2))
     den = (b ** 2).sum(axis=(0, 2))
-    den[:6] = np.maximum(den[:6], 1e-20 * den[:6].max())
-    den[6:9] = np.maximum(den[6:9], 1e-20 * den[6:9].max())
-    if len(den) > 9:
-        den[9:] = np.maximum(den[9:], 1e-20 * max(den[9:].max(), 1e-300))
+    for g0, g1 in ((0, 6), (6, 9), (9, len(den))):
+        if g1 > g0:
+            top = den[g0:g1].max()
+            # a kind that vanishes altogether is measured in absolute terms
+            den[g0:g1] = np.maximum(den[g0:g1], 1e-20 * top) if top > 0 else 1.0
     return np.sqrt(num / den)
 
 
