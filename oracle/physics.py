@@ -179,10 +179,14 @@ def godunov_matrices(An_m, An_p, n, kind):
         Gm[free] = I9[free] - Rin[free] @ np.linalg.solve(TR, Tr[free])
     absorb = kind == 2
     if np.any(absorb):
-        wl, Lt = _sorted_eig(np.transpose(An_m[absorb], (0, 2, 1)))  # left eigenvectors
-        Lin = Lt[:, :, :3]
-        P = np.transpose(Lin, (0, 2, 1)) @ Rin[absorb]                 # [f,3,3]
-        proj = Rin[absorb] @ np.linalg.solve(P, np.transpose(Lin, (0, 2, 1)))
+        # characteristic amplitudes alpha = R^-1 q- over the full eigenvector
+        # basis R of A_n^-: the rows of R^-1 are the left eigenvectors dual
+        # to exactly these right ones (a separate eigendecomposition of A_n^T
+        # may pair the degenerate S-wave spaces differently); the incoming
+        # amplitudes (the three most negative speeds) are removed
+        Ra = Rm[absorb]
+        amp = np.linalg.solve(Ra, np.broadcast_to(np.eye(9), Ra.shape))   # R^-1
+        proj = Ra[:, :, :3] @ amp[:, :3, :]
         Gm[absorb] = I9[absorb] - proj
     return Gm, Gp
 
