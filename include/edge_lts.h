@@ -162,6 +162,27 @@ int edg_set_receivers(edg_ctx* ctx, int64_t n, const double* xyz, double dt_samp
  * context's stream and returns after the work has completed. */
 int edg_advance_to(edg_ctx* ctx, double t);
 
+/* ---- allocation-free advance ----------------------------------------------
+ * For callers that cannot allocate device memory while they advance: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same as edg_advance_to, except that the B1 / B2 / B3 face
+ * traces, which one advance from a synchronisation point writes before it
+ * reads them, live in a static device array of EDG_STATIC_SCRATCH_BYTES per
+ * GPU (held from the first call on that GPU until the process ends) instead
+ * of the context's own buffers.  The call allocates nothing: no hipMalloc or
+ * hipFree, no graph instantiation, no event creation; every level launches
+ * eagerly (EDG_FLAG_GRAPH and timing do not apply).  The array is zeroed by a
+ * fill kernel at the start of each call.  DOFs, seismograms and the element
+ * update count are bit-identical to edg_advance_to.
+ * Errors: EDG_EINVAL if the context's traces, n_runs x (T1 + T2 + T3 words)
+ * x word bytes, exceed EDG_STATIC_SCRATCH_BYTES (the message gives both
+ * sizes; about 44,000 elements at O = 5, FP32, one run); EDG_ESTATE before
+ * edg_upload_clusters or with checkpointing on; EDG_ENOTSYNC as
+ * edg_advance_to.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (two threads, two contexts) race. */
+#define EDG_STATIC_SCRATCH_BYTES (256ull << 20)
+int edg_advance_to_static(edg_ctx* ctx, double t);
+
 /* Recorded seismograms of run `run` (0..n_runs-1): out [n_rec][n_samples][9];
  * cap = number of doubles available (EDG_ECAP if smaller). */
 int edg_read_receivers(edg_ctx* ctx, int32_t run, double* out, int64_t cap);

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("EDG_LIBRARY") or os.path.join(HERE, "lib", "libedge_lts.so")
 
 EDG_OK = 0
+STATIC_SCRATCH_BYTES = 256 << 20   # EDG_STATIC_SCRATCH_BYTES
 ERRORS = {-1: "EDG_EINVAL", -2: "EDG_ESTATE", -3: "EDG_ENOMEM", -4: "EDG_EHIP",
           -5: "EDG_ENOTSYNC", -6: "EDG_EMESH", -7: "EDG_ECAP"}
 BC_INTERIOR, BC_FREE, BC_ABSORB = 0, 1, 2
@@ -24,7 +25,7 @@ FLAG_GRAPH = 1
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = ["edg_create", "edg_upload_mesh", "edg_upload_materials", "edg_upload_clusters",
            "edg_get_clusters", "edg_set_initial", "edg_set_dofs_subset", "edg_read_dofs_subset", "edg_set_sources", "edg_set_receivers",
-           "edg_advance_to", "edg_read_receivers", "edg_read_dofs", "edg_time", "edg_last_error",
+           "edg_advance_to", "edg_advance_to_static", "edg_read_receivers", "edg_read_dofs", "edg_time", "edg_last_error",
            "edg_enable_timing", "edg_kernel_stats", "edg_element_updates", "edg_set_plan", "edg_get_plan",
            "edg_autotune", "edg_set_checkpointing", "edg_rewind", "edg_adjoint", "edg_destroy",
            "edg_reference_matrices", "edg_cluster_host", "edg_godunov_host"]
@@ -76,6 +77,7 @@ def lib():
             "edg_set_sources": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _I32, _P]),
             "edg_set_receivers": (ctypes.c_int, [_P, _I64, _P, ctypes.c_double, _I64]),
             "edg_advance_to": (ctypes.c_int, [_P, ctypes.c_double]),
+            "edg_advance_to_static": (ctypes.c_int, [_P, ctypes.c_double]),
             "edg_read_receivers": (ctypes.c_int, [_P, _I32, _P, _I64]),
             "edg_read_dofs": (ctypes.c_int, [_P, _I32, _P, _I64]),
             "edg_time": (ctypes.c_double, [_P]),
@@ -208,6 +210,11 @@ class Context:
     # --- stepping and output
     def advance_to(self, t):
         self._chk(self._L.edg_advance_to(self.h, float(t)))
+
+    def advance_to_static(self, t):
+        """edg_advance_to with the face traces in the library's static device
+        array: the call allocates nothing."""
+        self._chk(self._L.edg_advance_to_static(self.h, float(t)))
 
     def read_dofs(self, run=0):
         out = np.empty((self.K, self.nq, self.B))

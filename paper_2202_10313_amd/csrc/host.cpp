@@ -1257,13 +1257,28 @@ int capture_cycle(edg_ctx* c, const AdvanceArgs& A) {
 
 namespace {
 
+// words of the B1 / B2 / B3 face traces of every run (T1, T2, T3 in turn)
+size_t trace_words(const edg_ctx* c) { return (size_t)c->runs * (c->run_t1 + c->run_t2 + c->run_t3); }
+
 // nc >= 1 LTS cycles from the current synchronisation point: predict every
-// element, then the cycles (the last one only finishes its steps)
-int advance_cycles(edg_ctx* c, int64_t nc) {
+// element, then the cycles (the last one only finishes its steps).  traces:
+// null for the context's own trace buffers, else the base of trace_words(c)
+// words that hold them for this advance only (every level then launches
+// eagerly and untimed: no graph, no event).  Within one advance from a
+// synchronisation point every trace slot is written before it is read, so
+// the traces carry nothing between calls.
+int advance_cycles(edg_ctx* c, int64_t nc, char* traces = nullptr) {
   const int Nc = c->cfg.n_clusters;
   const int64_t per = (int64_t)1 << (Nc - 1);
-  const AdvanceArgs A = advance_args(c);
-  const bool graph = (c->cfg.flags & EDG_FLAG_GRAPH) != 0;
+  AdvanceArgs A = advance_args(c);
+  if (traces) {
+    const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+    A.p.T1 = traces;
+    A.p.T2 = traces + (size_t)c->runs * c->run_t1 * rs;
+    A.p.T3 = traces + (size_t)c->runs * (c->run_t1 + c->run_t2) * rs;
+  }
+  const bool timed = traces == nullptr;
+  const bool graph = timed && (c->cfg.flags & EDG_FLAG_GRAPH) != 0;
   c->ev_used = 0;
   c->ev_updates.clear();
   c->ev_launches.clear();
@@ -1273,7 +1288,7 @@ int advance_cycles(edg_ctx* c, int64_t nc) {
   a.kind = KIND_PREDICT;
   a.jrel = 0;
   a.end = c->cl_end[Nc - 1];
-  int rc = launch_timed(c, A.fn, A.p, a, 0);
+  int rc = timed ? launch_timed(c, A.fn, A.p, a, 0) : launch_runs(c, A.fn, A.p, a);
   if (rc) return rc;
   if (c->n_rec > 0 && (rc = A.fn.rec(A.p, a, A.ra, c->runs, c->stream)))
     return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
@@ -1284,7 +1299,7 @@ int advance_cycles(edg_ctx* c, int64_t nc) {
       if ((rc = timed_begin(c, cycle_updates(c), (int)per))) return rc;
       HIPCHK(c, hipGraphLaunch(c->cycle_exec, c->stream));
       if ((rc = timed_end(c))) return rc;
-    } else if ((rc = emit_cycle(c, A, last, true))) {
+    } else if ((rc = emit_cycle(c, A, last, timed))) {
       return rc;
     }
     c->updates += cycle_updates(c);
@@ -1389,7 +1404,50 @@ int advance_recorded(edg_ctx* c, int64_t nc) {
   return EDG_OK;
 }
 
+// whole LTS cycles from the current time to t (EDG_ENOTSYNC unless t is a
+// synchronisation point not before the current time)
+int cycles_until(edg_ctx* c, double t, int64_t* nc) {
+  const int Nc = c->cfg.n_clusters;
+  const double sync = c->dt_cl[Nc - 1];
+  const double t_now = (double)c->level * c->dt_cl[0];
+  const double cycles = (t - t_now) / sync;
+  const double ncd = std::nearbyint(cycles);
+  if (!(ncd >= 0) || std::fabs(cycles - ncd) > 1e-9 * std::max(1.0, std::fabs(cycles)))
+    return fail(c, EDG_ENOTSYNC, "time is not a synchronisation point after the current time");
+  *nc = (int64_t)ncd;
+  return 0;
+}
+
 }  // namespace
+
+namespace edg {
+
+// The allocation-free advance (edg_advance_to_static): the face traces of
+// this advance live in the caller-provided device memory [base, base + cap).
+int advance_to_traces(edg_ctx* c, double t, void* base, size_t cap) {
+  if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
+  if (c->ckpt_every > 0)
+    return fail(c, EDG_ESTATE, "the allocation-free advance stores no checkpoints: turn checkpointing off");
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  const size_t need = trace_words(c) * rs;
+  if (need > cap)
+    return fail(c, EDG_EINVAL, "the face traces of this context need " + std::to_string(need) +
+                                   " bytes; the static scratch holds " + std::to_string(cap));
+  int64_t nc = 0;
+  int rc = cycles_until(c, t, &nc);
+  if (rc || nc == 0) return rc;
+  // nothing is read before it is written, but the traces start from zeros
+  // as the context's own buffers do after an upload
+  if ((rc = launch_zero_words(base, need / 4, c->stream)))
+    return fail(c, EDG_EHIP, std::string("fill kernel: ") + hipGetErrorString((hipError_t)rc));
+  return advance_cycles(c, nc, (char*)base);
+}
+
+int ctx_device(const edg_ctx* c) { return c->cfg.device; }
+
+int ctx_fail(edg_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+
+}  // namespace edg
 
 extern "C" {
 
@@ -1397,15 +1455,9 @@ int edg_advance_to(edg_ctx* c, double t) {
   if (!c) return EDG_EINVAL;
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  const int Nc = c->cfg.n_clusters;
-  const double sync = c->dt_cl[Nc - 1];
-  const double t_now = (double)c->level * c->dt_cl[0];
-  const double cycles = (t - t_now) / sync;
-  const double ncd = std::nearbyint(cycles);
-  if (ncd < 0 || std::fabs(cycles - ncd) > 1e-9 * std::max(1.0, std::fabs(cycles)))
-    return fail(c, EDG_ENOTSYNC, "time is not a synchronisation point after the current time");
-  if (ncd == 0) return EDG_OK;
-  const int64_t nc = (int64_t)ncd;
+  int64_t nc = 0;
+  int rc0 = cycles_until(c, t, &nc);
+  if (rc0 || nc == 0) return rc0;
   if (c->ckpt_every <= 0) return advance_cycles(c, nc);
   // checkpointed: segments of at most ckpt_every cycles, each one an advance
   // of its own that starts from a stored state; the final one records its

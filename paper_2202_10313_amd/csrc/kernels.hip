@@ -33,6 +33,7 @@
 //    finish the step of every active element and start its next one.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -1063,6 +1064,18 @@ __global__ void k_tick(long long* clock, long long d) {
 
 int launch_tick(long long* clock, long long d, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, clock, d);
+  return (int)hipGetLastError();
+}
+
+__global__ void k_zero_words(uint32_t* p, size_t words) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0u;
+}
+
+int launch_zero_words(void* p, size_t words, hipStream_t st) {
+  if (words == 0) return 0;
+  const size_t blocks = std::min<size_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, words);
   return (int)hipGetLastError();
 }
 

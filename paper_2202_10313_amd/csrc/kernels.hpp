@@ -94,6 +94,8 @@ struct RecArgs {
 template <class R, int O, int M>
 int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st);
 int launch_tick(long long* clock, long long d, hipStream_t st);
+// zero `words` 32-bit words at p (a fill kernel: no memset node in a capture)
+int launch_zero_words(void* p, size_t words, hipStream_t st);
 template <class R, int O, int M>
 int launch_sources(const KPtrs& p, const LevelArgs& a, const SrcArgs& s, hipStream_t st);
 template <class R, int O, int M>
