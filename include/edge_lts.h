@@ -22,7 +22,12 @@
  *     no call aborts the process or throws across the ABI;
  *   - every array argument is a host pointer owned by the caller and is only
  *     read (or written, for outputs) during the call; the library copies
- *     what it keeps;
+ *     what it keeps.  The calls with an on_device argument take device
+ *     pointers instead when it is 1 (FP64 arrays in device memory of the
+ *     context's device, in the same layouts): they are read or written on
+ *     the context's stream during the call (the caller orders the work that
+ *     produces or consumes them with that stream) and the call returns after
+ *     that work has completed;
  *   - element data is in the caller's element order and the caller's local
  *     vertex order; internally elements are reordered by cluster and each
  *     tet's vertices are sorted by vertex id, which the library undoes on
@@ -102,14 +107,24 @@ int edg_create(const edg_config* cfg, edg_ctx** out);
 int edg_upload_mesh(edg_ctx* ctx, int64_t n_tets, const int64_t* tet_verts, const double* tet_xyz,
                     const int8_t* face_bc);
 
-/* Materials per element: density rho [kg/m^3], unrelaxed P and S speeds vp,
- * vs [m/s] (vs > 0); for m > 0, the relaxation frequencies omega [m] (rad/s,
- * shared by all elements) and the P/S weights yp, ys [K][m] of the
- * generalised Maxwell body (stress relaxes by -sum_l (a_l tr(theta^l) I +
- * b_l theta^l), a_l = (lambda+2mu) Yp_l - 2mu Ys_l, b_l = 2mu Ys_l; the memory
- * variables obey d/dt theta^l = omega_l (sym grad v - theta^l)). */
+/* Materials per element (Sec. III (ADER-DG Finite Element Method), eq.
+ * hyp_sys, whose Jacobians and anelastic source the paper takes from its
+ * references): density rho [kg/m^3], unrelaxed P and S speeds vp, vs [m/s]
+ * (rho > 0, vs > 0, vp > sqrt(4/3) vs, else EDG_EINVAL and nothing changes);
+ * for m > 0, the relaxation frequencies omega [m] (rad/s, shared by all
+ * elements) and the P/S weights yp, ys [K][m] of the generalised Maxwell body
+ * (stress relaxes by -sum_l (a_l tr(theta^l) I + b_l theta^l),
+ * a_l = (lambda+2mu) Yp_l - 2mu Ys_l, b_l = 2mu Ys_l; the memory variables
+ * obey d/dt theta^l = omega_l (sym grad v - theta^l)).  The weights are
+ * inputs, not quality factors: a constant-Q fit (Qp, Qs over a band) is the
+ * caller's, so that both sides of a comparison use the same weights.
+ * on_device = 1: all six arrays are device pointers; the range check and the
+ * per-element tables are then computed on the device (no host copy of the
+ * arrays unless a later edg_upload_clusters needs one).  After
+ * edg_upload_clusters a re-upload re-derives the operators but keeps the
+ * clusters, time steps and state (what a gradient check needs). */
 int edg_upload_materials(edg_ctx* ctx, const double* rho, const double* vp, const double* vs,
-                         const double* omega, const double* yp, const double* ys);
+                         const double* omega, const double* yp, const double* ys, int32_t on_device);
 
 /* Time clusters (Sec. V-A (Clustering)).  cluster: [K] values 1..N_c in the caller's
  * element order (used as given; EDG_EINVAL if two face neighbours differ by
@@ -184,8 +199,9 @@ int edg_advance_to(edg_ctx* ctx, double t);
 int edg_advance_to_static(edg_ctx* ctx, double t);
 
 /* Recorded seismograms of run `run` (0..n_runs-1): out [n_rec][n_samples][9];
- * cap = number of doubles available (EDG_ECAP if smaller). */
-int edg_read_receivers(edg_ctx* ctx, int32_t run, double* out, int64_t cap);
+ * cap = number of doubles available (EDG_ECAP if smaller); on_device = 1:
+ * out is a device pointer. */
+int edg_read_receivers(edg_ctx* ctx, int32_t run, double* out, int64_t cap, int32_t on_device);
 
 /* DOFs [K][Nq][B] of run `run` (0..n_runs-1) at the current time; cap = doubles
  * available. */
@@ -261,9 +277,12 @@ int edg_rewind(edg_ctx* ctx);
  * levels run backwards through the adjoint kernels.  A checkpoint interval
  * that covers the whole advance therefore needs no replay at all.  All host arrays are caller-owned and only read or written
  * during the call; the DOFs and the time are those of before the call when it
- * returns.  EDG_ESTATE without checkpoints or for n_runs > 1. */
+ * returns.  EDG_ESTATE without checkpoints or for n_runs > 1.  on_device = 1:
+ * all six arrays are device pointers; dj_dseis is copied and the gradients
+ * are scattered to caller order on the device, while dj_dq and g_q0 (DOF
+ * layout conversions done by the host) are staged through host memory. */
 int edg_adjoint(edg_ctx* ctx, const double* dj_dseis, const double* dj_dq, double* g_q0, double* g_rho,
-                double* g_vp, double* g_vs);
+                double* g_vp, double* g_vs, int32_t on_device);
 
 /* Destroy the context and free its device memory (NULL is ignored). */
 void edg_destroy(edg_ctx* ctx);

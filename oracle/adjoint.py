@@ -208,10 +208,11 @@ def _receivers_T(orc, idx, Db, seis_b):
         dt = orc.dt_elem[k]
         t0 = float(orc.nstep[k]) * dt
         t1 = float(orc.nstep[k] + 1) * dt
-        s = max(0, int(math.floor(t0 / dts)) - 1)
-        while s < orc.rec["ns"] and float(s) * dts < t1:
+        eps = 1e-9 * dt
+        s = max(0, int(math.floor((t0 - eps) / dts)) - 1)
+        while s < orc.rec["ns"] and float(s) * dts < t1 - eps:
             ts = float(s) * dts
-            if ts >= t0:
+            if ts >= t0 - eps:
                 for r in rs:
                     for d in range(orc.O):
                         w = (ts - t0) ** d / math.factorial(d)

@@ -27,7 +27,10 @@ Not in the paper ([reading]): point sources add -M phi(x_s)/|det J| times the
 exact integral of the moment rate over the step to the stress modes, at the
 end of the step of the source's element; receivers sample the element's
 Taylor expansion sum_d (t-t^n)^d/d! d^dQ(x_r) at the sample times inside the
-element's step, during its prediction (the 9 elastic quantities).
+element's step, during its prediction (the 9 elastic quantities); the step
+[t^n, t^n+dt) takes the samples in [t^n - eps, t^n + dt - eps), eps = 1e-9 dt,
+so a sample on a step boundary belongs to the step that starts there even
+where two implementations round the boundary differently.
 
 Pins: tests/test_oracle_solver.py (plane waves, convergence order, ODE case
 against expm, energy decay, momentum conservation, polynomial exactness,
@@ -336,10 +339,13 @@ class Oracle:
             dt = self.dt_elem[k]
             t0 = float(self.nstep[k]) * dt
             t1 = float(self.nstep[k] + 1) * dt
-            s = max(0, int(math.floor(t0 / dts)) - 1)
-            while s < self.rec["ns"] and float(s) * dts < t1:
+            # the step takes the samples in [t0 - eps, t1 - eps), eps = 1e-9 dt:
+            # a sample on a step boundary belongs to the step starting there
+            eps = 1e-9 * dt
+            s = max(0, int(math.floor((t0 - eps) / dts)) - 1)
+            while s < self.rec["ns"] and float(s) * dts < t1 - eps:
                 ts = float(s) * dts
-                if ts >= t0:
+                if ts >= t0 - eps:
                     for r in rs:
                         val = np.zeros(9)
                         for d in range(self.O):

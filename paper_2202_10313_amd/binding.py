@@ -68,7 +68,7 @@ def lib():
         sig = {
             "edg_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_P)]),
             "edg_upload_mesh": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
-            "edg_upload_materials": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+            "edg_upload_materials": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I32]),
             "edg_upload_clusters": (ctypes.c_int, [_P, _P]),
             "edg_get_clusters": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
             "edg_set_initial": (ctypes.c_int, [_P, _I32, _P]),
@@ -78,7 +78,7 @@ def lib():
             "edg_set_receivers": (ctypes.c_int, [_P, _I64, _P, ctypes.c_double, _I64]),
             "edg_advance_to": (ctypes.c_int, [_P, ctypes.c_double]),
             "edg_advance_to_static": (ctypes.c_int, [_P, ctypes.c_double]),
-            "edg_read_receivers": (ctypes.c_int, [_P, _I32, _P, _I64]),
+            "edg_read_receivers": (ctypes.c_int, [_P, _I32, _P, _I64, _I32]),
             "edg_read_dofs": (ctypes.c_int, [_P, _I32, _P, _I64]),
             "edg_time": (ctypes.c_double, [_P]),
             "edg_last_error": (ctypes.c_char_p, [_P]),
@@ -90,7 +90,7 @@ def lib():
             "edg_autotune": (ctypes.c_int, [_P, _I32, _P, _P]),
             "edg_set_checkpointing": (ctypes.c_int, [_P, _I32]),
             "edg_rewind": (ctypes.c_int, [_P]),
-            "edg_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+            "edg_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I32]),
             "edg_destroy": (None, [_P]),
             "edg_reference_matrices": (ctypes.c_int, [_I32, _P, _P]),
             "edg_cluster_host": (ctypes.c_int, [_I64, _P, _P, _I32, ctypes.c_double, _P, _P, _P]),
@@ -115,6 +115,18 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def _is_device(a):
+    return getattr(a, "is_cuda", False)
+
+
+def _dev_ptr(t):
+    """Device pointer of a contiguous float64 CUDA tensor (no copy)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("device arrays must be contiguous float64 CUDA tensors")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def n_basis(order):
@@ -166,8 +178,20 @@ class Context:
         self._chk(self._L.edg_upload_mesh(self.h, self.K, _ptr(tv), _ptr(xyz), _ptr(bc)))
 
     def upload_materials(self, rho, vp, vs, omega=None, yp=None, ys=None):
+        """Host arrays, or CUDA tensors (then every array is read from device
+        memory: on_device = 1; omega, yp, ys given on the host are moved to
+        rho's device first)."""
+        if _is_device(rho):
+            import torch
+            dev = rho.device
+            arrs = [a if a is None or _is_device(a) else torch.as_tensor(np.asarray(a, dtype=np.float64), device=dev)
+                    for a in (rho, vp, vs, omega, yp, ys)]
+            arrs = [None if a is None else a.to(torch.float64).contiguous() for a in arrs]
+            self._keep = arrs                # alive until the call returns
+            self._chk(self._L.edg_upload_materials(self.h, *[None if a is None else _dev_ptr(a) for a in arrs], 1))
+            return
         arrs = [_f64(a) for a in (rho, vp, vs, omega, yp, ys)]
-        self._chk(self._L.edg_upload_materials(self.h, *[_ptr(a) for a in arrs]))
+        self._chk(self._L.edg_upload_materials(self.h, *[_ptr(a) for a in arrs], 0))
 
     def upload_clusters(self, clusters=None):
         cl = None if clusters is None else np.ascontiguousarray(clusters, dtype=np.int32)
@@ -223,7 +247,14 @@ class Context:
 
     def read_receivers(self, run=0):
         out = np.zeros((self.n_rec, self.n_samples, 9))
-        self._chk(self._L.edg_read_receivers(self.h, run, _ptr(out), out.size))
+        self._chk(self._L.edg_read_receivers(self.h, run, _ptr(out), out.size, 0))
+        return out
+
+    def read_receivers_device(self, device, run=0):
+        """Seismograms as a float64 tensor on `device` (device-to-device copy)."""
+        import torch
+        out = torch.zeros((self.n_rec, self.n_samples, 9), dtype=torch.float64, device=device)
+        self._chk(self._L.edg_read_receivers(self.h, run, _dev_ptr(out), out.numel(), 1))
         return out
 
     def time(self):
@@ -264,7 +295,21 @@ class Context:
         qb = None if dj_dq is None else _f64(dj_dq, (self.K, self.nq, self.B))
         q0 = np.empty((self.K, self.nq, self.B)) if want_q0 else None
         g = [np.empty(self.K) for _ in range(3)]
-        self._chk(self._L.edg_adjoint(self.h, _ptr(sb), _ptr(qb), _ptr(q0), *[_ptr(a) for a in g]))
+        self._chk(self._L.edg_adjoint(self.h, _ptr(sb), _ptr(qb), _ptr(q0), *[_ptr(a) for a in g], 0))
+        return dict(q0_b=q0, g_rho=g[0], g_vp=g[1], g_vs=g[2])
+
+    def adjoint_device(self, dj_dseis, dj_dq=None, want_q0=False):
+        """edg_adjoint on device tensors (on_device = 1): dj_dseis [n_rec,
+        n_samples, 9] and dj_dq [K, Nq, B] CUDA float64 tensors (or None);
+        returns dict(q0_b, g_rho, g_vp, g_vs) as tensors on the same device."""
+        import torch
+        dev = dj_dseis.device
+        sb = dj_dseis.to(torch.float64).contiguous()
+        qb = None if dj_dq is None else dj_dq.to(torch.float64).contiguous()
+        q0 = torch.empty((self.K, self.nq, self.B), dtype=torch.float64, device=dev) if want_q0 else None
+        g = [torch.empty(self.K, dtype=torch.float64, device=dev) for _ in range(3)]
+        self._chk(self._L.edg_adjoint(self.h, _dev_ptr(sb), None if qb is None else _dev_ptr(qb),
+                                      None if q0 is None else _dev_ptr(q0), *[_dev_ptr(a) for a in g], 1))
         return dict(q0_b=q0, g_rho=g[0], g_vp=g[1], g_vs=g[2])
 
     def autotune(self, cycles=1):

@@ -43,7 +43,8 @@ def build(verbose: bool = False) -> str:
           os.path.join(CSRC, "basis.cpp")])
     _run([gen, os.path.join(CSRC, "generated", "refmats.h")] + ORDERS)
     units = [("kernels.hip", "kernels.o"), ("adjoint.hip", "adjoint.o"), ("host.cpp", "host.o"),
-             ("basis.cpp", "basis.o"), ("noalloc.hip", "noalloc.o")]
+             ("basis.cpp", "basis.o"), ("noalloc.hip", "noalloc.o"),
+             ("materials.hip", "materials.o")]
 
     def compile_unit(u):
         src, obj = u

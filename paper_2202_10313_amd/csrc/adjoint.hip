@@ -1627,12 +1627,14 @@ __global__ void k_receivers_adj(KPtrs p, APtrs ad, LevelArgs a, RecArgs r, const
   const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
   double vb[O];
   for (int d = 0; d < O; ++d) vb[d] = 0.0;
-  long long s = (long long)floor(t0 / r.dt_sample) - 1;
+  // the samples of step n: [t0 - eps, t1 - eps), eps = 1e-9 dt (as sampled)
+  const double eps = 1e-9 * dt, lo = t0 - eps, hi = t1 - eps;
+  long long s = (long long)floor(lo / r.dt_sample) - 1;
   if (s < 0) s = 0;
   bool any = false;
-  for (; s < r.ns && (double)s * r.dt_sample < t1; ++s) {
+  for (; s < r.ns && (double)s * r.dt_sample < hi; ++s) {
     const double ts = (double)s * r.dt_sample;
-    if (ts < t0) continue;
+    if (ts < lo) continue;
     const double x = ts - t0, sb = seis_b[((size_t)rec * r.ns + s) * LPE + q];
     double pw = 1.0, fact = 1.0;
     for (int d = 0; d < O; ++d) {

@@ -113,6 +113,12 @@ struct edg_ctx {
   // completed reverse sweep: each is cleared by its reader)
   bool adj_clean = false;
   bool amat_valid = false;           // amat holds the materials of the current upload, internal order
+  // materials uploaded from device memory: a device copy in caller order
+  // (rho, vp, vs [K], yp, ys [K][m]); the host vectors are refreshed from it
+  // when host code needs them
+  bool mat_host_valid = true;
+  DevBuf dmat, dflag;
+  DevBuf d_i2u, d_nbr;               // internal_to_user [Kp], nbr [K][4] (int64, for device-side tables)
   int64_t hist_L0 = 0, hist_J = 0;
   // adjoint buffers
   DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal, amat, agrad;
@@ -277,6 +283,31 @@ void cluster_all(int64_t K, const double* dt, const int64_t* nbr, int Nc, double
       first = false;
     }
   }
+}
+
+// the host copies of the materials (after an upload from device memory they
+// are fetched from the library's device copy when host code first needs them)
+int ensure_host_materials(edg_ctx* c) {
+  if (c->mat_host_valid) return 0;
+  const int64_t K = c->K;
+  const int M = c->M;
+  const double* d = (const double*)c->dmat.p;
+  c->rho.resize(K);
+  c->vp.resize(K);
+  c->vs.resize(K);
+  c->yp.resize((size_t)K * M);
+  c->ys.resize((size_t)K * M);
+  HIPCHK(c, hipMemcpyAsync(c->rho.data(), d, K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->vp.data(), d + K, K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->vs.data(), d + 2 * K, K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (M > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->yp.data(), d + 3 * K, K * M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ys.data(), d + 3 * K + K * M, K * M * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->mat_host_valid = true;
+  return 0;
 }
 
 template <class R>
@@ -721,7 +752,7 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
 edg_ctx::~edg_ctx() {
   for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
                     &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock, &aLe, &aLa, &aS0, &aS1, &aS2, &aS3, &aDe, &aDa,
-                    &agacc, &arecDb, &aseis, &ahist, &afinal, &amat, &agrad})
+                    &agacc, &arecDb, &aseis, &ahist, &afinal, &amat, &agrad, &dmat, &dflag, &d_i2u, &d_nbr})
     dev_free(*b);
   for (auto& ck : ckpts) dev_free(ck.second);
   for (auto& e : ev_pool) {
@@ -868,12 +899,72 @@ int edg_upload_mesh(edg_ctx* c, int64_t K, const int64_t* tv, const double* xyz,
   return EDG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// edg_upload_materials with device pointers: range check on the device
+// (nothing changes if it fails), a device copy of the caller's arrays, and
+// the material words of the tables rebuilt on the device
+template <class R>
+int upload_materials_device(edg_ctx* c, const double* rho, const double* vp, const double* vs, const double* omega,
+                            const double* yp, const double* ys) {
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const int64_t K = c->K;
+  const int M = c->M;
+  int rc;
+  if ((rc = dev_reserve(c, c->dflag, sizeof(unsigned)))) return rc;
+  HIPCHK(c, hipMemsetAsync(c->dflag.p, 0, sizeof(unsigned), c->stream));
+  const MatIn in{rho, vp, vs, M > 0 ? yp : nullptr, M > 0 ? ys : nullptr};
+  if ((rc = launch_check_materials(in, K, (unsigned*)c->dflag.p, c->stream)))
+    return fail(c, EDG_EHIP, std::string("material check kernel: ") + hipGetErrorString((hipError_t)rc));
+  unsigned bad = 0;
+  std::vector<double> om(M);
+  HIPCHK(c, hipMemcpyAsync(&bad, c->dflag.p, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+  if (M > 0) HIPCHK(c, hipMemcpyAsync(om.data(), omega, M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad) return fail(c, EDG_EINVAL, std::to_string(bad) + " elements have materials out of range");
+  const size_t mw = 3 + 2 * (size_t)M;
+  if ((rc = dev_reserve(c, c->dmat, (size_t)K * mw * sizeof(double)))) return rc;
+  double* d = (double*)c->dmat.p;
+  HIPCHK(c, hipMemcpyAsync(d, rho, K * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d + K, vp, K * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d + 2 * K, vs, K * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (M > 0) {
+    HIPCHK(c, hipMemcpyAsync(d + 3 * K, yp, K * M * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + 3 * K + K * M, ys, K * M * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  c->omega = om;
+  c->mat_host_valid = false;
+  c->have_mat = true;
+  drop_checkpoints(c);
+  c->amat_valid = false;
+  if (c->have_clusters) {   // re-derive the material words of the tables, keep clusters and state
+    const MatIn own{d, d + K, d + 2 * K, M > 0 ? d + 3 * K : nullptr, M > 0 ? d + 3 * K + K * M : nullptr};
+    if ((rc = dev_reserve(c, c->amat, (size_t)c->Kp * mw * sizeof(double)))) return rc;
+    if ((rc = launch_pack_materials<R>(own, M, c->Kp, (const long long*)c->d_i2u.p, (const long long*)c->d_nbr.p,
+                                       (R*)c->P.p, (double*)c->amat.p, c->stream)))
+      return fail(c, EDG_EHIP, std::string("material table kernel: ") + hipGetErrorString((hipError_t)rc));
+    c->amat_valid = true;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int edg_upload_materials(edg_ctx* c, const double* rho, const double* vp, const double* vs, const double* omega,
-                         const double* yp, const double* ys) {
+                         const double* yp, const double* ys, int32_t on_device) {
   if (!c) return EDG_EINVAL;
   if (!c->have_mesh) return fail(c, EDG_ESTATE, "upload the mesh first");
   if (!rho || !vp || !vs) return fail(c, EDG_EINVAL, "null material array");
   if (c->M > 0 && (!omega || !yp || !ys)) return fail(c, EDG_EINVAL, "anelastic run needs omega, yp, ys");
+  if (on_device != 0 && on_device != 1) return fail(c, EDG_EINVAL, "on_device must be 0 or 1");
+  if (on_device)
+    return c->cfg.fp64 ? upload_materials_device<double>(c, rho, vp, vs, omega, yp, ys)
+                       : upload_materials_device<float>(c, rho, vp, vs, omega, yp, ys);
   const int64_t K = c->K;
   for (int64_t k = 0; k < K; ++k)
     if (!(rho[k] > 0) || !(vs[k] > 0) || !(vp[k] > std::sqrt(4.0 / 3.0) * vs[k]))
@@ -889,6 +980,7 @@ int edg_upload_materials(edg_ctx* c, const double* rho, const double* vp, const 
     c->omega.clear();
   }
   c->have_mat = true;
+  c->mat_host_valid = true;
   drop_checkpoints(c);
   c->amat_valid = false;
   if (c->have_clusters) {  // re-derive operators, keep clusters and state
@@ -911,6 +1003,8 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   if (!c) return EDG_EINVAL;
   if (!c->have_mesh || !c->have_mat) return fail(c, EDG_ESTATE, "upload mesh and materials first");
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  int rc = ensure_host_materials(c);
+  if (rc) return rc;
   drop_checkpoints(c);
   c->amat_valid = false;
   const int64_t K = c->K;
@@ -963,7 +1057,9 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   }
   // device state: tables shared by the runs, then every run's state
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
-  int rc;
+  if ((rc = dev_upload(c, c->d_i2u, c->internal_to_user.data(), c->Kp * sizeof(int64_t))) ||
+      (rc = dev_upload(c, c->d_nbr, c->nbr.data(), c->nbr.size() * sizeof(int64_t))))
+    return rc;
   if (c->cfg.fp64) {
     std::vector<double> P;
     pack_tables<double>(c, P, c->FI_host);
@@ -1525,14 +1621,21 @@ int edg_autotune(edg_ctx* c, int32_t cycles, edg_plan* best_out, double* best_ms
   return EDG_OK;
 }
 
-int edg_read_receivers(edg_ctx* c, int32_t run, double* out, int64_t cap) {
+int edg_read_receivers(edg_ctx* c, int32_t run, double* out, int64_t cap, int32_t on_device) {
   if (!c) return EDG_EINVAL;
   if (run < 0 || run >= c->runs || !out) return fail(c, EDG_EINVAL, "bad run or null output");
+  if (on_device != 0 && on_device != 1) return fail(c, EDG_EINVAL, "on_device must be 0 or 1");
   const int64_t need = (int64_t)c->n_rec * c->rec_ns * LPE;
   if (cap < need) return fail(c, EDG_ECAP, "output capacity too small");
   if (need == 0) return EDG_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
-  HIPCHK(c, hipMemcpy(out, (double*)c->r_out.p + (size_t)run * need, need * sizeof(double), hipMemcpyDeviceToHost));
+  const double* src = (const double*)c->r_out.p + (size_t)run * need;
+  if (on_device) {
+    HIPCHK(c, hipMemcpyAsync(out, src, need * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    HIPCHK(c, hipMemcpy(out, src, need * sizeof(double), hipMemcpyDeviceToHost));
+  }
   return EDG_OK;
 }
 
@@ -1567,7 +1670,7 @@ namespace {
 // reverse sweep over the checkpointed segments (see edg_adjoint)
 template <class R, int O, int M>
 int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double* g_q0, double* g_rho, double* g_vp,
-                  double* g_vs) {
+                  double* g_vs, bool dev) {
   const int Nc = c->cfg.n_clusters, B = c->B, FP = c->FP, JB = jb_count(c);
   const size_t rs = sizeof(R), we = c->run_qe, wa = c->run_qa;
   const size_t slot_words = (size_t)4 * ADJ_ROWS * FP;
@@ -1605,10 +1708,24 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
     for (DevBuf* b : {&c->aS0, &c->aS1, &c->aS2, &c->aS3, &c->arecDb})
       HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (dj_q && (rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) return rc;
-  if (dj_seis && c->n_rec > 0)
-    HIPCHK(c, hipMemcpy(c->aseis.p, dj_seis, (size_t)c->n_rec * c->rec_ns * LPE * sizeof(double),
-                        hipMemcpyHostToDevice));
+  if (dj_q) {
+    if (dev) {   // the DOF layout conversion runs on the host: stage through host memory
+      std::vector<double> h((size_t)c->K * c->NQ * c->B);
+      HIPCHK(c, hipMemcpy(h.data(), dj_q, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+      if ((rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, h.data()))) return rc;
+    } else if ((rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) {
+      return rc;
+    }
+  }
+  if (dj_seis && c->n_rec > 0) {
+    const size_t bytes = (size_t)c->n_rec * c->rec_ns * LPE * sizeof(double);
+    if (dev) {
+      HIPCHK(c, hipMemcpyAsync(c->aseis.p, dj_seis, bytes, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+      HIPCHK(c, hipMemcpy(c->aseis.p, dj_seis, bytes, hipMemcpyHostToDevice));
+    }
+  }
   // the replays run on a state of their own, so the context's DOFs stay
   // those of the final time
   char* rep_state = (char*)c->afinal.p;
@@ -1678,11 +1795,20 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   // outputs
-  if (g_q0 && (rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, g_q0))) return rc;
+  if (g_q0) {
+    if (dev) {
+      std::vector<double> h((size_t)c->K * c->NQ * c->B);
+      if ((rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, h.data()))) return rc;
+      HIPCHK(c, hipMemcpy(g_q0, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else if ((rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, g_q0))) {
+      return rc;
+    }
+  }
   if (g_rho || g_vp || g_vs) {
     // chain rule on the device (gathers over face neighbours), then reorder
     // (the material table is uploaded once per material / cluster upload)
     if (!c->amat_valid) {
+      if ((rc = ensure_host_materials(c))) return rc;
       const int mw = 3 + 2 * c->M;
       std::vector<double> mat((size_t)c->Kp * mw, 0.0);
       for (int64_t k = 0; k < c->K; ++k) {
@@ -1704,14 +1830,22 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
                                            c->M, c->Kp, (double*)c->agrad.p, c->stream),
                   "material gradient kernel")))
       return rc;
-    std::vector<double> gi((size_t)c->Kp * 3);
-    HIPCHK(c, hipMemcpyAsync(gi.data(), c->agrad.p, gi.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int64_t k = 0; k < c->K; ++k) {
-      const double* x = &gi[(size_t)c->user_to_internal[k] * 3];
-      if (g_rho) g_rho[k] = x[0];
-      if (g_vp) g_vp[k] = x[1];
-      if (g_vs) g_vs[k] = x[2];
+    if (dev) {
+      if ((rc = chk(launch_scatter_gradient((const double*)c->agrad.p, (const long long*)c->d_i2u.p, c->Kp, g_rho,
+                                            g_vp, g_vs, c->stream),
+                    "gradient scatter kernel")))
+        return rc;
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+      std::vector<double> gi((size_t)c->Kp * 3);
+      HIPCHK(c, hipMemcpyAsync(gi.data(), c->agrad.p, gi.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (int64_t k = 0; k < c->K; ++k) {
+        const double* x = &gi[(size_t)c->user_to_internal[k] * 3];
+        if (g_rho) g_rho[k] = x[0];
+        if (g_vp) g_vp[k] = x[1];
+        if (g_vs) g_vs[k] = x[2];
+      }
     }
   }
   const long long clock_end = (long long)L_end;
@@ -1720,7 +1854,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   return EDG_OK;
 }
 
-typedef int (*AdjFn)(edg_ctx*, const double*, const double*, double*, double*, double*, double*);
+typedef int (*AdjFn)(edg_ctx*, const double*, const double*, double*, double*, double*, double*, bool);
 
 AdjFn pick_adjoint(int fp64, int O, int M) {
   AdjFn f = nullptr;
@@ -1736,8 +1870,9 @@ AdjFn pick_adjoint(int fp64, int O, int M) {
 extern "C" {
 
 int edg_adjoint(edg_ctx* c, const double* dj_dseis, const double* dj_dq, double* g_q0, double* g_rho, double* g_vp,
-                double* g_vs) {
+                double* g_vs, int32_t on_device) {
   if (!c) return EDG_EINVAL;
+  if (on_device != 0 && on_device != 1) return fail(c, EDG_EINVAL, "on_device must be 0 or 1");
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
   if (c->runs != 1) return fail(c, EDG_ESTATE, "the adjoint needs a single run");
   if (c->ckpt_every <= 0 || c->ckpts.empty())
@@ -1747,7 +1882,7 @@ int edg_adjoint(edg_ctx* c, const double* dj_dseis, const double* dj_dq, double*
   HIPCHK(c, hipStreamSynchronize(c->stream));
   AdjFn f = pick_adjoint(c->cfg.fp64, c->O, c->M);
   if (!f) return fail(c, EDG_EINVAL, "no adjoint kernel for this order / mechanism count");
-  return f(c, dj_dseis, dj_dq, g_q0, g_rho, g_vp, g_vs);
+  return f(c, dj_dseis, dj_dq, g_q0, g_rho, g_vp, g_vs, on_device != 0);
 }
 
 double edg_time(const edg_ctx* c) { return c ? (double)c->level * c->dt_cl[0] : 0.0; }

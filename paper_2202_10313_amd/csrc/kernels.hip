@@ -1039,11 +1039,15 @@ __global__ void k_receivers(KPtrs p, LevelArgs a, RecArgs r) {
     for (int b = 0; b < B; ++b) v += (double)D[((size_t)d * LPE + q) * B + b] * r.phi[(size_t)rec * B + b];
     val[d] = v;
   }
-  long long s = (long long)floor(t0 / r.dt_sample) - 1;
+  // step n takes the samples in [t0 - eps, t1 - eps), eps = 1e-9 dt: a sample
+  // on (or within rounding of) a step boundary belongs to the step that
+  // starts there, whichever way the two sides round the boundary
+  const double eps = 1e-9 * dt, lo = t0 - eps, hi = t1 - eps;
+  long long s = (long long)floor(lo / r.dt_sample) - 1;
   if (s < 0) s = 0;
-  for (; s < r.ns && (double)s * r.dt_sample < t1; ++s) {
+  for (; s < r.ns && (double)s * r.dt_sample < hi; ++s) {
     const double ts = (double)s * r.dt_sample;
-    if (ts < t0) continue;
+    if (ts < lo) continue;
     const double x = ts - t0;
     double acc = 0.0, pw = 1.0, fact = 1.0;
     for (int d = 0; d < O; ++d) {

@@ -91,6 +91,29 @@ struct RecArgs {
   double* out;            // [run][n][ns][9]
 };
 
+// materials in device memory, caller's element order: rho, vp, vs [K];
+// yp, ys [K][M] (null for M = 0)
+struct MatIn {
+  const double* rho;
+  const double* vp;
+  const double* vs;
+  const double* yp;
+  const double* ys;
+};
+// adds the number of elements with rho <= 0, vs <= 0 or vp <= sqrt(4/3) vs to *bad
+int launch_check_materials(const MatIn& m, long long K, unsigned* bad, hipStream_t st);
+// the material words of the parameter table P [Kp][NPARAM] (1/rho, lambda,
+// mu, Zp, Zs, a_l, b_l, the face neighbours' Zp, Zs) and the adjoint's
+// material rows amat [Kp][3 + 2M] (rho, vp, vs, Yp_l, Ys_l; zeros for
+// padding); i2u [Kp]: caller index of each internal slot (-1: padding);
+// nbr [K][4]: caller index of the neighbour across each sorted-frame face
+template <class R>
+int launch_pack_materials(const MatIn& m, int M, long long Kp, const long long* i2u, const long long* nbr, R* P,
+                          double* amat, hipStream_t st);
+// g [Kp][3] (internal order) -> g_rho, g_vp, g_vs [K] (caller order; any may be null)
+int launch_scatter_gradient(const double* g, const long long* i2u, long long Kp, double* g_rho, double* g_vp,
+                            double* g_vs, hipStream_t st);
+
 template <class R, int O, int M>
 int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st);
 int launch_tick(long long* clock, long long d, hipStream_t st);

@@ -262,3 +262,36 @@ def test_receivers_on_shared_vertices_and_faces():
     es = seis_parity(ctx.read_receivers(), orc.seis)
     print(f"receivers on shared vertices / faces: {es:.3e}")
     assert es <= TOL64
+
+
+@pytest.mark.parametrize("order,fp64,div", [(3, True, 1), (3, True, 2), (5, False, 1)])
+def test_receivers_on_step_boundaries(order, fp64, div):
+    """Samples every finest step (div = 1) or half step (div = 2): every
+    sample time sits on a step boundary of the finest cluster, every 2^l-th
+    on one of cluster l as well.  Both sides give a boundary sample to the
+    step that starts there (each step takes [t^n - eps, t^n + dt - eps),
+    eps = 1e-9 dt, which absorbs the last-bit differences between their
+    independently computed steps), so the seismograms agree; the sample at
+    the end of the window belongs to the next, not yet predicted step and is
+    zero on both."""
+    w = anelastic_setup("tiny", order, 3)
+    ctx = gpu_context(w, order, 3, fp64)
+    info = ctx.get_clusters()
+    dts = info["lam"] * info["dt_min"] / div
+    t = 2 * info["sync_dt"]
+    ns = int(round(t / dts)) + 1
+    orc = Oracle(w["mesh"], w["mat"], order, attn=w["attn"], n_clusters=3, lam=None, sources=w["src"],
+                 receivers=dict(xyz=w["rec"], dt_sample=dts, n_samples=ns))
+    q0 = synth.random_state(9, orc.K, 27, orc.B)
+    orc.set_initial(q0)
+    ctx.set_initial(q0)
+    ctx.set_sources(w["src"]["xyz"], w["src"]["moment"], w["src"]["stf_kind"], w["src"]["stf_params"])
+    ctx.set_receivers(w["rec"], dts, ns)
+    orc.run(t)
+    ctx.advance_to(t)
+    seis = ctx.read_receivers()
+    es = seis_parity(seis, orc.seis)
+    print(f"receivers on step boundaries O={order} {'FP64' if fp64 else 'FP32'} dt/{div}: {es:.3e}")
+    assert es <= (TOL64 if fp64 else TOL32)
+    assert np.all(seis[:, -1] == 0) and np.all(orc.seis[:, -1] == 0)
+    assert np.all(np.any(seis[:, :-1] != 0, axis=2))
