@@ -23,6 +23,12 @@ source (fc uniform in 1-3 Hz, random moment tensor, uniform location in the
 top 5 km), and reports run-element updates per second against the plain
 single-run value.
 
+Extra workload lines (--configs): "c3_basin" the 7.88M-tet graded basin
+(O=5, N_c=5, 400 subfaults, 256 receivers; a few timed cycles, the wall time
+of 10 simulated seconds extrapolated), "c4_fused_o4" 16 runs at O=4 against
+the plain O=4 run, "c5_gradient_o4" the 201,720-tet gradient workload (O=4,
+N_c=2, elastic and anelastic, 4 s, a checkpoint every 50 cycles).
+
 The "adjoint" entry times the gradient of a receiver misfit with respect to
 rho, vp, vs over a short window: the checkpointed forward plus the reverse
 sweep, against the plain forward of the same cycles.  Its main figure keeps
@@ -114,6 +120,13 @@ def algorithmic_bytes_per_update(cl, nbr, order, m, n_clusters, word=4):
     return float(np.sum(per * weight) / np.sum(weight))
 
 
+def fractions(rate, bytes_per_update, flops_per_update):
+    """HBM, FP32 and combined roofline fractions of an element-update rate."""
+    hbm = rate * bytes_per_update / (HBM_PEAK_GBS * 1e9)
+    fp32 = rate * flops_per_update / (FP32_PEAK_TFLOPS * 1e12) if flops_per_update else 0.0
+    return {"hbm": hbm, "fp32": fp32 if flops_per_update else None, "combined": max(hbm, fp32)}
+
+
 def _oracle_sample(cycles):
     """One oracle run of the CPU-baseline sample (runs in a worker process):
     returns (element updates, wall seconds, CPU seconds)."""
@@ -191,6 +204,12 @@ def main():
     ap.add_argument("--fused-steps", type=int, default=4)
     ap.add_argument("--adjoint-steps", type=int, default=2,
                     help="cycles of the forward + adjoint (gradient) line (0: skip it)")
+    ap.add_argument("--configs", default="c3,c4,c5",
+                    help="extra workload lines: c3 (7.88M-tet basin, N_c=5), c4 (16 fused runs at O=4), "
+                         "c5 (200k-tet gradient workload); '' for none")
+    ap.add_argument("--c3-cycles", type=int, default=3, help="timed LTS cycles of the basin line")
+    ap.add_argument("--c4-steps", type=int, default=4, help="timed LTS cycles of the O=4 fused line")
+    ap.add_argument("--c5-seconds", type=float, default=4.0, help="simulated time of the gradient line")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch every level eagerly")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false", help="keep the default launch plan")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -294,6 +313,143 @@ def main():
         if not all(np.all(np.isfinite(g[k])) for k in ("g_rho", "g_vp", "g_vs")):
             raise RuntimeError("non-finite gradient")
         ctx.close()
+        return out
+
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    def line_c3():
+        """The graded basin (one GPU's share of a high-frequency run): 7.88M
+        tets, O=5, m=3, N_c=5, FP32, 400 Hann subfaults, 256 receivers; one
+        untimed cycle, then --c3-cycles timed; the wall time of the 10 s
+        simulation is extrapolated from the timed cycles."""
+        say("c3: generating the 7.88M-tet basin")
+        bm = synth.basin_box("full", seed=30)
+        bmat = synth.basin_materials(bm, 31)
+        battn = synth.attenuation_inputs(bmat, 3, 0.1, 10.0)
+        fault = synth.kinematic_fault(32, (2000.0, -1500.0, -7000.0))
+        brec = synth.surface_receivers(33, 256, ((-20000.0, 20000.0), (-20000.0, 20000.0)))
+        ctx = Context(5, mechanisms=3, n_clusters=5, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream,
+                      flags=FLAG_GRAPH if args.graph else 0)
+        ctx.upload_mesh(bm["tet_verts"], bm["tet_xyz"], bm["face_bc"])
+        ctx.upload_materials(bmat["rho"], bmat["vp"], bmat["vs"], battn["omega"], battn["yp"], battn["ys"])
+        say("c3: clustering and uploading")
+        ctx.upload_clusters(None)
+        inf = ctx.get_clusters()
+        sy = inf["sync_dt"]
+        ctx.set_sources(fault["xyz"], fault["moment"], fault["stf_kind"], fault["stf_params"])
+        ctx.set_receivers(brec, 0.01, 1001)
+        ctx.set_plan(xcd_remap=1)
+        ctx.advance_to(sy)
+        u0 = ctx.element_updates()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.advance_to((1 + args.c3_cycles) * sy)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        upd = ctx.element_updates() - u0
+        if not np.all(np.isfinite(ctx.read_receivers())):
+            raise RuntimeError("non-finite seismograms in the basin line")
+        ctx.close()
+        bcl = inf["clusters"].astype(np.int64)
+        bpu = algorithmic_bytes_per_update(bcl, face_neighbours(bm["tet_verts"]), 5, 3, 5)
+        rate = upd / wall
+        cycles_10s = 10.0 / sy
+        say(f"c3: {rate:.4g} element updates/s, {wall / args.c3_cycles * 1e3:.1f} ms per cycle")
+        return {"workload": f"graded basin, {bm['tet_verts'].shape[0]} tets, O=5, m=3, N_c=5, FP32, 400 Hann "
+                            f"subfaults, 256 receivers; step = one LTS cycle ({2 ** 4} finest levels)",
+                "value": rate, "unit": "elem-updates/s", "steps": args.c3_cycles,
+                "ms_per_step": wall / args.c3_cycles * 1e3, "lambda": inf["lam"],
+                "cluster_sizes": np.bincount(bcl, minlength=6)[1:].tolist(),
+                "theoretical_lts_speedup": inf["speedup"],
+                "gts_equivalent_rate": bm["tet_verts"].shape[0] * (args.c3_cycles * sy / inf["dt_min"]) / wall,
+                "simulated_10s": {"cycles": cycles_10s, "wall_s_extrapolated": cycles_10s * wall / args.c3_cycles},
+                "algorithmic_bytes_per_update": bpu,
+                "roofline": fractions(rate, bpu, PAPER_FLOPS_ALL_SPARSITY)}
+
+    def line_c4():
+        """16 independent runs at O=4 in one context against the plain O=4 run
+        (the rate of 16 sequential plain runs is 16 runs x the plain rate)."""
+        say(f"c4: plain O=4, 1 run, warmup 1, {args.c4_steps} cycles")
+        pl = measure(4, 1, args.c4_steps, 1)
+        say(f"c4: fused O=4, 16 runs, warmup 1, {args.c4_steps} cycles")
+        fu = measure(4, 16, args.c4_steps, 1)
+        pv, fv = pl["updates"] / pl["wall"], fu["updates"] / fu["wall"]
+        bpu4 = algorithmic_bytes_per_update(cl, nbr, 4, 3, 3)
+        say(f"c4: {fv:.4g} run-element updates/s against {pv:.4g} plain ({fv / pv:.2f}x)")
+        return {"workload": f"16 runs of the layered box, {K} tets, O=4, m=3, N_c=3, FP32, one Ricker per run",
+                "runs": 16, "value": fv, "unit": "run-elem-updates/s", "plain_value": pv,
+                "ratio_vs_16_sequential_plain_runs": fv / pv, "steps": args.c4_steps,
+                "ms_per_step": fu["wall"] * 1e3 / args.c4_steps, "plain_ms_per_step": pl["wall"] * 1e3 / args.c4_steps,
+                "launch_plan": fu["plan"], "plain_launch_plan": pl["plan"],
+                "algorithmic_bytes_per_update": bpu4, "roofline_plain": fractions(pv, bpu4, None),
+                "roofline_fused": fractions(fv, bpu4, None)}
+
+    def line_c5():
+        """The gradient workload: 201,720 tets, O=4, N_c=2, FP32, elastic and
+        anelastic; misfit J = 1/2 sum (s - d)^2 dt against data d from a
+        +-3% perturbed model over --c5-seconds; forward with a checkpoint
+        every 50 LTS cycles (all but the final segment replayed by the
+        sweep) plus the reverse sweep, against the plain forward."""
+        dm = synth.differentiation_box("full", seed=50)
+        dmat = synth.layered_materials(dm, 51)
+        dattn = synth.attenuation_inputs(dmat, 3, 0.05, 5.0)
+        dsrc = synth.ricker_sources(52, 1, ((3000.0, 7000.0), (3000.0, 7000.0)), (1000.0, 3000.0), fc_range=(2.0, 2.0))
+        drec = synth.surface_receivers(53, 32, ((500.0, 9500.0), (500.0, 9500.0)))
+        rng = np.random.default_rng(54)
+        Kd = dm["tet_verts"].shape[0]
+        pert = {k: dmat[k] * (1 + rng.uniform(-0.03, 0.03, Kd)) for k in ("rho", "vp", "vs")}
+        out = {"workload": f"layered 10x10x5 km box, {Kd} tets, O=4, N_c=2, FP32, 1 Ricker, 32 receivers, "
+                           f"{args.c5_seconds} s; misfit against a +-3% perturbed model",
+               "checkpoint_every_cycles": 50}
+        for mech in (0, 3):
+            ctx = Context(4, mechanisms=mech, n_clusters=2, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream,
+                          flags=FLAG_GRAPH if args.graph else 0)
+            ctx.upload_mesh(dm["tet_verts"], dm["tet_xyz"], dm["face_bc"])
+            extra = (dattn["omega"], dattn["yp"], dattn["ys"]) if mech else ()
+            ctx.upload_materials(dmat["rho"], dmat["vp"], dmat["vs"], *extra)
+            ctx.upload_clusters(None)
+            inf = ctx.get_clusters()
+            sy = inf["sync_dt"]
+            ncyc = max(1, int(round(args.c5_seconds / sy)))
+            dts = 0.005
+            ctx.set_sources(dsrc["xyz"], dsrc["moment"], STF_RICKER, dsrc["stf_params"])
+            ctx.set_receivers(drec, dts, int(ncyc * sy / dts) + 2)
+            say(f"c5 m={mech}: data from the perturbed model, {ncyc} cycles")
+            ctx.upload_materials(pert["rho"], pert["vp"], pert["vs"], *extra)
+            ctx.advance_to(ncyc * sy)
+            d = ctx.read_receivers()
+            ctx.upload_materials(dmat["rho"], dmat["vp"], dmat["vs"], *extra)
+            ctx.rewind()
+            u0 = ctx.element_updates()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.advance_to(ncyc * sy)
+            torch.cuda.synchronize()
+            plain = time.perf_counter() - t0
+            upd = ctx.element_updates() - u0
+            ctx.rewind()
+            ctx.set_checkpointing(50)
+            say(f"c5 m={mech}: checkpointed forward + reverse sweep")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.advance_to(ncyc * sy)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s_ = ctx.read_receivers()
+            g = ctx.adjoint(dj_dseis=(s_ - d) * dts, want_q0=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if not all(np.all(np.isfinite(g[k])) and np.any(g[k] != 0) for k in ("g_rho", "g_vp", "g_vs")):
+                raise RuntimeError("non-finite or zero gradient in the gradient line")
+            ctx.close()
+            out["anelastic" if mech else "elastic"] = {
+                "cycles": ncyc, "lambda": inf["lam"], "cluster_sizes": np.bincount(inf["clusters"], minlength=3)[1:].tolist(),
+                "plain_forward_s": plain, "plain_rate": upd / plain,
+                "forward_checkpointed_s": t1 - t0, "reverse_sweep_s": t2 - t1,
+                "cost_vs_plain_forward": (t2 - t0) / plain, "reverse_vs_plain_forward": (t2 - t1) / plain,
+                "misfit": 0.5 * float(np.sum((s_ - d) ** 2) * dts)}
+            say(f"c5 m={mech}: forward + gradient {(t2 - t0) / plain:.2f}x the plain forward ({plain:.2f} s)")
         return out
 
     print(f"[bench] plain: 1 run, O={args.order}, warmup {args.warmup}, {args.steps} cycles", file=sys.stderr, flush=True)
@@ -405,6 +561,13 @@ def main():
         out["fused"] = fused
     if adjoint is not None:
         out["adjoint"] = adjoint
+    extra = [c.strip() for c in args.configs.split(",") if c.strip()]
+    if "c4" in extra:
+        out["c4_fused_o4"] = line_c4()
+    if "c5" in extra:
+        out["c5_gradient_o4"] = line_c5()
+    if "c3" in extra:
+        out["c3_basin"] = line_c3()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

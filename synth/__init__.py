@@ -269,6 +269,17 @@ def loh_like_box(scale: str = "full", seed: int = 20) -> dict:
     raise ValueError(scale)
 
 
+def differentiation_box(scale: str = "full", seed: int = 50) -> dict:
+    """The 10 x 10 x 5 km layered box of the gradient workload (free surface on
+    top, absorbing elsewhere): 41 x 41 columns, layers 4 x 100 m, 3 x 200 m,
+    13 x 307.7 m, jitter 10%, K = 201,720.  'small' is the 2 x 2 x 1 km box
+    of loh_like_box('small') (K = 5,082) used for the oracle comparison."""
+    if scale == "full":
+        return layered_box(41, 41, [100.0] * 4 + [200.0] * 3 + [307.7] * 13, 10000.0, 10000.0,
+                           jitter=0.10, seed=seed)
+    return loh_like_box(scale, seed=seed)
+
+
 # --------------------------------------------------------------------------- graded basin workload
 
 def graded_box(xs, ys, zs, jitter: float = 0.0, seed: int = 0, top_bc: int = BC_FREE,
