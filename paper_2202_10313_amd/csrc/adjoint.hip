@@ -1171,7 +1171,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) pm[((2 * w + ii) * LPE + q) * FS + f] = pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) pm[(RF::tface(w, ii) * LPE + q) * FS + f] = pt[ii * FP + f];
     }
     __syncthreads();
     // items (face i, mode f), spread over both waves' lanes of the element;

@@ -515,6 +515,11 @@ void k_level2(KPtrs p, LevelArgs a) {
   constexpr int JW = (NBX + LPE - 1) / LPE;      // owned memory modes per lane
   constexpr int JB = (B + LPE - 1) / LPE;        // memory-variable layout
   __shared__ R lds[L::TOTAL];
+  // per element and face: normal, area ratio, neighbour impedances (the face
+  // words of the parameter table) and the boundary kind, staged for the
+  // Godunov items of the surface phase
+  __shared__ R fdat[KIND != KIND_PREDICT ? EPW * 4 * 8 : 1];
+  __shared__ int fbc[KIND != KIND_PREDICT ? EPW * 4 : 1];
 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave (uniform)
   const int lane = threadIdx.x & 63;
@@ -620,6 +625,13 @@ void k_level2(KPtrs p, LevelArgs a) {
     const R* T1 = reinterpret_cast<const R*>(p.T1);
     const R* T2 = reinterpret_cast<const R*>(p.T2);
     const R* T3 = reinterpret_cast<const R*>(p.T3);
+    if (w == 0 && q < 4 && e < EPW) {
+      const R* fp = P + 20 + 6 * q;
+      R* d = fdat + (ec * 4 + q) * 8;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) d[k] = fp[k];
+      fbc[ec * 4 + q] = (FI[3 * q + 1] >> 4) & 15;
+    }
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii) {
       const int i = 2 * w + ii;
@@ -666,9 +678,8 @@ void k_level2(KPtrs p, LevelArgs a) {
       const int t = q + LPE * (w + 2 * rr);
       if (t < 4 * F) {
         const int i = t / F, f = t % F;
-        const int code = FI[3 * i + 1];
-        const int bc = (code >> 4) & 15;
-        const R* fp = P + 20 + 6 * i;
+        const int bc = fbc[ec * 4 + i];
+        const R* fp = fdat + (ec * 4 + i) * 8;
         R qm[9], qp[9], out[15];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -894,7 +905,7 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-        for (int f = 0; f < FP; ++f) T1[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+        for (int f = 0; f < FP; ++f) T1[own + RF::tface(w, ii) * LPE * FP + f] = pt[ii * FP + f];
     }
     if ((eflags & EF_HAS_COARSER) && valid) {
       R* T3 = reinterpret_cast<R*>(p.T3) + ((size_t)((nn >> 1) & 1) * p.N3 + (size_t)FI[14]) * tstride;
@@ -902,12 +913,12 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T3[q * FP + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) T3[q * FP + RF::tface(w, ii) * LPE * FP + f] = pt[ii * FP + f];
       } else {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-          for (int f = 0; f < FP; ++f) T3[q * FP + (2 * w + ii) * LPE * FP + f] += pt[ii * FP + f];
+          for (int f = 0; f < FP; ++f) T3[q * FP + RF::tface(w, ii) * LPE * FP + f] += pt[ii * FP + f];
       }
     }
     if (w == 0) RF::vol_grad_p0(full, G, gw0, gw1, gw2);
@@ -955,7 +966,7 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-        for (int f = 0; f < FP; ++f) T2[own + (2 * w + ii) * LPE * FP + f] = pt[ii * FP + f];
+        for (int f = 0; f < FP; ++f) T2[own + RF::tface(w, ii) * LPE * FP + f] = pt[ii * FP + f];
     }
   }
 
