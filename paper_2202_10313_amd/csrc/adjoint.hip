@@ -930,7 +930,9 @@ struct AdjLds2 {
 __device__ __forceinline__ int aslot(int row, int dir) {
   constexpr int T[9][3] = {{9, 18, 18}, {18, 10, 18}, {18, 18, 11}, {12, 13, 18}, {18, 14, 15},
                            {16, 18, 17}, {0, 1, 2}, {3, 4, 5}, {6, 7, 8}};
-  return T[row][dir];
+  constexpr unsigned long long W0 = pack_rows5(T, 0), W1 = pack_rows5(T, 1), W2 = pack_rows5(T, 2);
+  const unsigned long long w = dir == 0 ? W0 : (dir == 1 ? W1 : W2);   // selects, no table in memory
+  return (int)((w >> (5 * row)) & 31);
 }
 
 template <class R, int O, int M>

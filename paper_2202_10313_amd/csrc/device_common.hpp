@@ -21,6 +21,15 @@ __device__ __forceinline__ int sym_index(int i, int j) {
   return a == 0 ? (b == 1 ? 3 : 5) : 4;
 }
 
+// A 9 x 3 table of small ints (< 32) packed 5 bits per row into one 64-bit
+// word per column: looking up a lane-dependent row is then a shift, not a
+// load from constant memory (which would cost a memory round trip).
+constexpr unsigned long long pack_rows5(const int (&T)[9][3], int col) {
+  unsigned long long w = 0;
+  for (int r = 0; r < 9; ++r) w |= (unsigned long long)T[r][col] << (5 * r);
+  return w;
+}
+
 __device__ __forceinline__ int cluster_of(const LevelArgs& a, int elem) {
   int c = 0;
 #pragma unroll

@@ -497,7 +497,9 @@ __device__ __forceinline__ int fresh(int v) {
 __device__ __forceinline__ int gslot(int row, int dir) {
   constexpr int T[9][3] = {{1, 18, 18}, {18, 6, 18}, {18, 18, 13}, {17, 12, 18}, {18, 14, 7},
                            {16, 18, 15}, {0, 2, 5}, {11, 10, 3}, {4, 8, 9}};
-  return T[row][dir];
+  constexpr unsigned long long W0 = pack_rows5(T, 0), W1 = pack_rows5(T, 1), W2 = pack_rows5(T, 2);
+  const unsigned long long w = dir == 0 ? W0 : (dir == 1 ? W1 : W2);   // selects, no table in memory
+  return (int)((w >> (5 * row)) & 31);
 }
 
 // KIND is the launch kind (KIND_PREDICT, KIND_FUSED, KIND_NEIGHBOR) as a
@@ -552,6 +554,22 @@ void k_level2(KPtrs p, LevelArgs a) {
   const R* P = reinterpret_cast<const R*>(p.P) + (size_t)g * EPW * NPARAM + ec * NPARAM;
   const int* FI = p.FI + (size_t)g * EPW * FI_WORDS + ec * FI_WORDS;
   const size_t tg = (size_t)g * EPW * TS;        // this workgroup's first trace
+
+  // The face records of the wave's two faces (and the face word codes to be
+  // staged) are the first loads of the kernel: the neighbour gathers depend
+  // on them, and loads complete in issue order.
+  int fnb[2] = {-1, -1}, fcd[2] = {0, 0}, fax[2] = {0, 0};
+  int fcode = 0;
+  const bool stage = KIND != KIND_PREDICT && w == 0 && q < 4 && e < EPW;
+  if constexpr (KIND != KIND_PREDICT) {
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+      fnb[ii] = FI[3 * (2 * w + ii)];
+      fcd[ii] = FI[3 * (2 * w + ii) + 1];
+      fax[ii] = FI[3 * (2 * w + ii) + 2];
+    }
+    if (stage) fcode = FI[3 * q + 1];
+  }
 
   const bool is_stress = q < 6;
   int qi = 0, qj = 0;
@@ -625,52 +643,68 @@ void k_level2(KPtrs p, LevelArgs a) {
     const R* T1 = reinterpret_cast<const R*>(p.T1);
     const R* T2 = reinterpret_cast<const R*>(p.T2);
     const R* T3 = reinterpret_cast<const R*>(p.T3);
-    if (w == 0 && q < 4 && e < EPW) {
-      const R* fp = P + 20 + 6 * q;
+    // the face words go to LDS after the gathers are issued (a store of a
+    // loaded value waits for it)
+    R fw[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (stage)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) fw[k] = P[20 + 6 * q + k];
+    // Neighbour data of the wave's two faces.  Each lane selects its sources
+    // by arithmetic (same cluster: the neighbour's B1; finer: its B3;
+    // coarser: its B2 in the first half step, B1 - B2 in the second; none:
+    // zeros) and every load of both faces is issued before any is used, so
+    // the memory latency is paid once rather than once per source kind.
+    R vown[2][FP], v1[2][FP], v2[2][FP];
+    bool none[2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+      const int i = 2 * w + ii;
+      const int nbr = fnb[ii];
+      const int code = fcd[ii];
+      const size_t aux = (size_t)fax[ii];
+      const int j = code & 15, rel = ((code >> 8) & 15) - 1;
+      const R* own = T1 + (size_t)(n & 1) * Kp * tstride + tg + (ec * TS + (i * LPE + q) * FP);
+      const size_t fo = (size_t)(j * LPE + q) * FP;
+      const int c = (n >> 1) & 1;
+      const R* b1 = T1 + (size_t)(rel == 0 ? (n & 1) : c) * Kp * tstride + (size_t)nbr * tstride + fo;
+      const R* b2 = T2 + ((size_t)c * p.N2 + aux) * tstride + fo;
+      const R* b3 = T3 + ((size_t)(n & 1) * p.N3 + aux) * tstride + fo;
+      const bool odd = (n & 1) != 0;
+      const R* s1 = nbr < 0 ? own : (rel == 0 ? b1 : (rel < 0 ? b3 : (odd ? b1 : b2)));
+      const bool sub = nbr >= 0 && rel > 0 && odd;
+      none[ii] = nbr < 0;
+      // (v2 is zeroed before its masked load: no write to a register with a
+      // load in flight)
+#pragma unroll
+      for (int f = 0; f < FP; ++f) v2[ii][f] = R(0);
+#pragma unroll
+      for (int f = 0; f < FP; ++f) vown[ii][f] = own[f];
+#pragma unroll
+      for (int f = 0; f < FP; ++f) v1[ii][f] = s1[f];
+      if (sub)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) v2[ii][f] = b2[f];
+    }
+    if (stage) {
       R* d = fdat + (ec * 4 + q) * 8;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) d[k] = fp[k];
-      fbc[ec * 4 + q] = (FI[3 * q + 1] >> 4) & 15;
+      for (int k = 0; k < 6; ++k) d[k] = fw[k];
+      fbc[ec * 4 + q] = fcode;
     }
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii) {
       const int i = 2 * w + ii;
-      const int nbr = FI[3 * i];
-      const int code = FI[3 * i + 1];
-      const size_t aux = (size_t)FI[3 * i + 2];
-      const int j = code & 15, rel = ((code >> 8) & 15) - 1;
-      const R* own = T1 + (size_t)(n & 1) * Kp * tstride + tg + (ec * TS + (i * LPE + q) * FP);
       R* dmn = fac + ((i * 2 + 0) * LPE + q) * FS;
       R* dpl = fac + ((i * 2 + 1) * LPE + q) * FS;
 #pragma unroll
-      for (int f = 0; f < FP; ++f) dmn[f] = own[f];
-      if (nbr >= 0) {
-        const size_t nbo = (size_t)nbr * tstride + (size_t)(j * LPE + q) * FP;
-        if (rel == 0) {
-          const R* s = T1 + (size_t)(n & 1) * Kp * tstride + nbo;
-#pragma unroll
-          for (int f = 0; f < FP; ++f) dpl[f] = s[f];
-        } else if (rel < 0) {
-          const R* s = T3 + ((size_t)(n & 1) * p.N3 + aux) * tstride + (size_t)(j * LPE + q) * FP;
-#pragma unroll
-          for (int f = 0; f < FP; ++f) dpl[f] = s[f];
-        } else {
-          const int c = (n >> 1) & 1;
-          const R* s2 = T2 + ((size_t)c * p.N2 + aux) * tstride + (size_t)(j * LPE + q) * FP;
-          if ((n & 1) == 0) {
-#pragma unroll
-            for (int f = 0; f < FP; ++f) dpl[f] = s2[f];
-          } else {
-            const R* s1 = T1 + (size_t)c * Kp * tstride + nbo;
-#pragma unroll
-            for (int f = 0; f < FP; ++f) dpl[f] = s1[f] - s2[f];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int f = 0; f < FP; ++f) dpl[f] = R(0);
+      for (int f = 0; f < FP; ++f) {
+        dmn[f] = vown[ii][f];
+        dpl[f] = none[ii] ? R(0) : v1[ii][f] - v2[ii][f];
       }
     }
+    // keep the state loads below behind these stores (the scheduler would
+    // otherwise interleave them and wait for all loads before the barrier)
+    __builtin_amdgcn_sched_barrier(0);
     load_state();
     __syncthreads();
 #pragma unroll 2
@@ -678,7 +712,7 @@ void k_level2(KPtrs p, LevelArgs a) {
       const int t = q + LPE * (w + 2 * rr);
       if (t < 4 * F) {
         const int i = t / F, f = t % F;
-        const int bc = fbc[ec * 4 + i];
+        const int bc = (fbc[ec * 4 + i] >> 4) & 15;
         const R* fp = fdat + (ec * 4 + i) * 8;
         R qm[9], qp[9], out[15];
 #pragma unroll
