@@ -105,6 +105,17 @@ __host__ __device__ __forceinline__ void godunov(const R* qm, const R* qp, R nx,
   out[14] = hs * (nx * vz + nz * vx);
 }
 
+// Orders the LDS accesses of one wave: every lane's LDS stores before it are
+// seen by every lane's LDS loads after it.  A wave's LDS instructions are
+// performed in issue order, so no hardware barrier is needed; the fences keep
+// the compiler from moving LDS accesses across.  For data written and read
+// by the same wave only (a workgroup barrier where other waves are involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Steps of cluster cl at the processed level (see LevelArgs::clock).
 __device__ __forceinline__ int step_new_of(const LevelArgs& a, int cl) {
   return (int)((*a.clock + a.jrel) >> cl);

@@ -754,8 +754,11 @@ void k_level2(KPtrs p, LevelArgs a) {
         for (int lb = 0; lb < NBX; ++lb)
           if (lb < nb) coup[q * BS + base + lb] = da[lb];
       coup_pending = true;
+      // the mode owners below read the coupling rows of their own wave's modes
+      wave_lds_sync();
+    } else {
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   if (M > 0 && coup_pending) {
@@ -769,7 +772,7 @@ void k_level2(KPtrs p, LevelArgs a) {
           for (int c = 0; c < 6; ++c) qa[jw][l][c] += om[l] * coup[c * BS + b];
     }
   }
-  if (M > 0 && coup_pending) __syncthreads();
+  // (the next LDS stores follow the workgroup barrier that forms need_b2)
 
   if constexpr (KIND == KIND_NEIGHBOR) {
     if (valid) {
@@ -894,7 +897,9 @@ void k_level2(KPtrs p, LevelArgs a) {
             for (int c = 0; c < 6; ++c) coup[c * BS + b] = cp[c];
         }
       }
-      __syncthreads();
+      // the coupling rows of a mode are read by the stress rows of the same
+      // wave (the wave that owns the mode)
+      wave_lds_sync();
     }
     // reads of three modes, then their stores of the next derivative (a store
     // into the row exchange between reads would, for the compiler, possibly
