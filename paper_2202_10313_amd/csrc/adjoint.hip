@@ -239,8 +239,28 @@ __device__ __forceinline__ const T& at(const T* base, uint32_t i) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (size_t)(i * (uint32_t)sizeof(T)));
 }
 
-// adds v to the element's gradient word w (LDS, FP64)
+// adds v to the element's gradient word w (LDS, FP64).  The elements' word
+// arrays are NGS = NG + 1 doubles apart: with a stride of NG = 48 doubles the
+// same word of every other element fell into one bank, so an atomic of a
+// wave serialised over four elements' lanes
+constexpr int NGS = NG + 1;
 __device__ __forceinline__ void gadd(double* gs, int w, double v) { atomicAdd(gs + w, v); }
+
+// DPP row shift right by N within 16-lane rows; lanes shifted in from
+// outside the row read 0
+template <int N>
+__device__ __forceinline__ float dpp_row_shr(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 + N, 0xf, 0xf, true));
+}
+// the sum of v over the lanes of its 16-lane row (an inclusive scan by
+// shifts 1, 2, 4, 8): complete in the row's last lane
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp_row_shr<1>(v);
+  v += dpp_row_shr<2>(v);
+  v += dpp_row_shr<4>(v);
+  v += dpp_row_shr<8>(v);
+  return v;
+}
 
 // UPD: the transposed update (KIND_ADJ_UPDATE) only needs the weighted
 // memory-variable rows in LDS, so it is its own instantiation with a small
@@ -258,7 +278,7 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
   constexpr bool NM_LDS = sizeof(R) == 8 && M > 0 && !UPD;
   constexpr int RSTRIDE = UPD ? 6 * B : L::REGION;   // LDS words per element
   __shared__ R lds[EPW * RSTRIDE];
-  __shared__ double gsh[UPD ? 1 : EPW * NG];
+  __shared__ double gsh[UPD ? 1 : EPW * NGS];
   __shared__ R nmsh[(NM_LDS ? JB * MM * 6 : 1) * 64];
 
   const int lane = threadIdx.x;
@@ -272,7 +292,7 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
   const bool valid = act && (elem < a.cl_vend[cl]);
   const int slot = ec * LPE + q;
   R* const reg = lds + ec * RSTRIDE;
-  double* const gs = gsh + ec * NG;
+  double* const gs = gsh + ec * NGS;
   const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
   const int* FI = p.FI + (size_t)elem * FI_WORDS;
   R* const Le = reinterpret_cast<R*>(ad.Le);
@@ -403,7 +423,7 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
   }
 
   // ================================================================ ADJ_PREDICT
-  for (int w = lane; w < EPW * NG; w += 64) gsh[w] = 0.0;
+  for (int w = lane; w < EPW * NGS; w += 64) gsh[w] = 0.0;
   const int nn = step_new_of(a, cl);
   const int eflags = FI[12];
   const bool has_b2 = (eflags & EF_HAS_FINER) != 0;
@@ -886,7 +906,7 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
   }
   __syncthreads();
   if (valid)
-    for (int w = q; w < NG; w += LPE) ad.gacc[(size_t)elem * NG + w] += gsh[ec * NG + w];
+    for (int w = q; w < NG; w += LPE) ad.gacc[(size_t)elem * NG + w] += gsh[ec * NGS + w];
 }
 
 // ---------------------------------------------------------------------------
@@ -948,7 +968,12 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   constexpr int JB = (B + LPE - 1) / LPE;        // memory-variable layout
   constexpr int BS = L::BS, FS = L::FS;
   __shared__ R lds[L::TOTAL];
-  __shared__ double gsh[EPW * NG];
+  __shared__ double gsh[EPW * NGS];
+  constexpr int FSTW = 17;
+  __shared__ R fst[EPW * 4 * FSTW];
+  __shared__ int fbc[EPW * 4];
+  __shared__ R emat[EPW * 5];
+  __shared__ int eint[EPW * 4];
 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -964,7 +989,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   // the long loops, so the compiler recomputes addresses there instead of
   // hoisting (and spilling) one per access
   int slot = ec * LPE + q;
-  const int base = w ? RF::MB1 : 0;
+  int base = w ? RF::MB1 : 0;                      // opaque at the loop tops (see slot)
   int jb0 = (base + q) / LPE;                      // memory-variable block of the lane's first owned mode
   const int nb = w ? NB1 : NB0;
   R* const reg = lds + ec * L::REGION;
@@ -972,7 +997,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   R* const coup = reg + L::GRAD;
   R* const rx = reg + L::GRAD + L::COUP;
   R* const pm = reg;                               // face area (overlaps grad / coup)
-  double* const gs = gsh + ec * NG;
+  double* const gs = gsh + ec * NGS;
   const R* P = reinterpret_cast<const R*>(p.P) + (size_t)elem * NPARAM;
   const int* FI = p.FI + (size_t)elem * FI_WORDS;
   R* const Le = reinterpret_cast<R*>(ad.Le) + (size_t)g * B * NSLOT;
@@ -1021,7 +1046,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   const R* const gt1 = grad + (aslot(q, 1) == 18 ? 19 : aslot(q, 1)) * BS;
   const R* const gt2 = grad + (aslot(q, 2) == 18 ? 19 : aslot(q, 2)) * BS;
 
-  for (int i = threadIdx.x; i < EPW * NG; i += 128) gsh[i] = 0.0;
+  for (int i = threadIdx.x; i < EPW * NGS; i += 128) gsh[i] = 0.0;
 
   const int nn = step_new_of(a, cl);
   const int eflags = FI[12];
@@ -1029,6 +1054,44 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   const bool has_b3 = (eflags & EF_HAS_COARSER) != 0;
   const bool any_b2 = __syncthreads_or(has_b2);
   const int rec_slot = FI[15];
+  // the parameters of each (element, face) pair the transposed surface reads,
+  // staged in LDS once (the face items then read no global parameter): the
+  // own face words (normal, area weight, outer impedances), the neighbour's
+  // 1/rho, lam, mu, Zp, Zs and its words of the shared face; fbc holds the
+  // boundary kind and a has-neighbour bit (16)
+  {
+    const int u = w * LPE + q;
+#pragma unroll
+    for (int k = 0; k < (4 * FSTW + 2 * LPE - 1) / (2 * LPE); ++k) {
+      const int idx = u + 2 * LPE * k;
+      if (act && idx < 4 * FSTW) {
+        const int i = idx / FSTW, wd = idx % FSTW;
+        const int nbr = FI[3 * i], code = FI[3 * i + 1];
+        R v = R(0);
+        if (wd < 6) {
+          v = P[20 + 6 * i + wd];
+        } else if (nbr >= 0) {
+          const R* Pn = reinterpret_cast<const R*>(p.P) + (size_t)nbr * NPARAM;
+          v = wd < 11 ? Pn[9 + (wd - 6)] : Pn[20 + 6 * (code & 15) + (wd - 11)];
+        }
+        fst[(ec * 4 + i) * FSTW + wd] = v;
+        if (wd == 0) fbc[ec * 4 + i] = ((code >> 4) & 15) | (nbr >= 0 ? 16 : 0);
+      }
+    }
+  }
+  // the element words the face items of other lanes read: (1/rho, lam, mu,
+  // Zp, Zs) and (valid, own B2 slot, own B3 slot, flags)
+  if (w == 0 && act && q == 0) {
+    emat[ec * 5 + 0] = rho_inv;
+    emat[ec * 5 + 1] = lam;
+    emat[ec * 5 + 2] = mu;
+    emat[ec * 5 + 3] = zp;
+    emat[ec * 5 + 4] = zs;
+    eint[ec * 4 + 0] = valid ? 1 : 0;
+    eint[ec * 4 + 1] = FI[13];
+    eint[ec * 4 + 2] = FI[14];
+    eint[ec * 4 + 3] = eflags;
+  }
 
   // ---------------------------------------------- forward recompute: D_d, T, T2
   R te[NBX], t2[NBX];
@@ -1052,7 +1115,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     }
 #pragma unroll 1
     for (int d = 0; d < O; ++d) {
-      asm volatile("" : "+v"(slot), "+v"(jb0));
+      asm volatile("" : "+v"(slot), "+v"(jb0), "+s"(base));
       const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
       const bool more = d + 1 < O;
       __syncthreads();
@@ -1151,14 +1214,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   R* const S1 = reinterpret_cast<R*>(ad.S1);
   R* const S2 = reinterpret_cast<R*>(ad.S2);
   R* const S3 = reinterpret_cast<R*>(ad.S3);
-  // the face words of the element (neighbour, code) for all four faces, read
-  // once: the items below select theirs, so their neighbour-parameter loads
-  // do not wait for an index load first
-  int fnb[4], fcode[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) { fnb[i] = FI[3 * i]; fcode[i] = FI[3 * i + 1]; }
   const int slot2 = FI[13], slot3 = FI[14];
-  auto face_phase = [&](const bool b2phase, const R* tint, R* acc) {
+  auto face_phase = [&](const bool b2phase, const R (&tint)[NBX], R (&acc)[NBX]) {
     if (act)
 #pragma unroll
       for (int lb = 0; lb < NBX; ++lb)
@@ -1176,52 +1233,69 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
           for (int f = 0; f < FP; ++f) pm[(RF::tface(w, ii) * LPE + q) * FS + f] = pt[ii * FP + f];
     }
     __syncthreads();
-    // items (face i, mode f), spread over both waves' lanes of the element;
-    // the own flux's element-wide words (1/rho, lam, mu, Zp, Zs) are summed
-    // per lane over the items and added once
-    double own5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // items (face i, mode f) of the whole group, one 16-lane DPP row per
+    // (element, face) pair: row r = 8 rr + 4 w + lane / 16 takes element
+    // r % 7 and face r / 7 (r < 28), lane f = lane % 16 its mode f (f < F).
+    // A row's 15 modes are contiguous in the slot buffers and in the trace
+    // area, and its gradient words are summed over the row with DPP and added
+    // once by the row's last lane (which holds no item): the LDS atomics are
+    // one lane per row instead of nine lanes per element.
+    const int f = lane & 15;
 #pragma unroll 1
-    for (int rr = 0; rr < (4 * F + 2 * LPE - 1) / (2 * LPE); ++rr) {
-      const int t = q + LPE * (w + 2 * rr);
-      if (t < 4 * F && act) {
-        const int i = t / F, f = t % F;
-        const int code = i == 0 ? fcode[0] : i == 1 ? fcode[1] : i == 2 ? fcode[2] : fcode[3];
-        const int nbr = i == 0 ? fnb[0] : i == 1 ? fnb[1] : i == 2 ? fnb[2] : fnb[3];
-        const int bc = (code >> 4) & 15;
-        const bool nflux = nbr >= 0 && valid;
-        // every global operand of the item first (one memory latency per item)
-        R u0[15], u1[15], fpv[6], pnv[5], fnv[6];
-        const R* fp = P + 20 + 6 * i;
+    for (int rr = 0; rr < (4 * EPW + 7) / 8; ++rr) {
+      const int r8 = 8 * rr + 4 * w + (lane >> 4);
+      const bool pair = r8 < 4 * EPW;
+      const int pe = pair ? r8 % EPW : 0, i = pair ? r8 / EPW : 0;
+      const int* const ei = eint + pe * 4;
+      const bool pvalid = pair && ei[0] != 0;
+      const int fb = fbc[pe * 4 + i];
+      const int bc = fb & 15;
+      const bool nflux = (fb & 16) && pvalid;             // a neighbour across face i
+      R pbo[7], pbn[7];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) fpv[k] = fp[k];
+      for (int k = 0; k < 7; ++k) { pbo[k] = R(0); pbn[k] = R(0); }
+      if (pair && f < F) {
+        const size_t pel = (size_t)g * EPW + pe;
+        const int eflg = ei[3];
+        // every global operand of the item first, into registers zeroed
+        // beforehand, and no use inside the branches that load them: one
+        // memory latency per item
+        R u0[15], ua[15], ub[15];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) { u0[k] = R(0); ua[k] = R(0); ub[k] = R(0); }
         if (!b2phase) {
-          const R* x = S0 + (size_t)elem * sstride + (size_t)i * ADJ_ROWS * FP + f;
+          const R* x = S0 + pel * sstride + (size_t)i * ADJ_ROWS * FP + f;
 #pragma unroll
-          for (int k = 0; k < 15; ++k) u0[k] = (M > 0 || k < 9) ? x[k * FP] : R(0);
+          for (int k = 0; k < 15; ++k)
+            if (M > 0 || k < 9) u0[k] = x[k * FP];
         }
-#pragma unroll
-        for (int k = 0; k < 15; ++k) u1[k] = R(0);
-        R* const s1 = !nflux ? nullptr : b2phase ? (has_b2 ? S2 + (size_t)slot2 * sstride : nullptr)
-                                                 : S1 + (size_t)elem * sstride;
-        R* const s3 = (nflux && !b2phase && has_b3) ? S3 + (size_t)slot3 * sstride : nullptr;
+        R* const s1 = !nflux ? nullptr
+                      : b2phase ? ((eflg & EF_HAS_FINER) ? S2 + (size_t)ei[1] * sstride : nullptr)
+                                : S1 + pel * sstride;
+        R* const s3 = (nflux && !b2phase && (eflg & EF_HAS_COARSER)) ? S3 + (size_t)ei[2] * sstride : nullptr;
         if (s1) {
-          R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
+          const R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
 #pragma unroll
-          for (int k = 0; k < 15; ++k) u1[k] += x[k * FP];
+          for (int k = 0; k < 15; ++k)
+            if (M > 0 || k < 9) ua[k] = x[k * FP];
         }
         if (s3) {
-          R* x = s3 + (size_t)i * ADJ_ROWS * FP + f;
+          const R* x = s3 + (size_t)i * ADJ_ROWS * FP + f;
 #pragma unroll
-          for (int k = 0; k < 15; ++k) u1[k] += x[k * FP];
+          for (int k = 0; k < 15; ++k)
+            if (M > 0 || k < 9) ub[k] = x[k * FP];
         }
-        if (nflux) {
-          const R* Pn = reinterpret_cast<const R*>(p.P) + (size_t)nbr * NPARAM;
-          const R* fn = Pn + 20 + 6 * (code & 15);
+        const R* const fs = fst + (pe * 4 + i) * FSTW;
+        const R* const em = emat + pe * 5;
+        R fpv[6], pnv[5], fnv[6], ev[5];
 #pragma unroll
-          for (int k = 0; k < 5; ++k) pnv[k] = Pn[9 + k];
+        for (int k = 0; k < 6; ++k) fpv[k] = fs[k];
 #pragma unroll
-          for (int k = 0; k < 6; ++k) fnv[k] = fn[k];
-        }
+        for (int k = 0; k < 5; ++k) pnv[k] = fs[6 + k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fnv[k] = fs[11 + k];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ev[k] = em[k];
         // the slots read are cleared (B3 only after its even step)
         if (s1) {
           R* x = s1 + (size_t)i * ADJ_ROWS * FP + f;
@@ -1233,42 +1307,49 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
           for (int k = 0; k < 15; ++k) x[k * FP] = R(0);
         }
-        R tr[9], zero9[9], tb[9], ob[9], pb[7];
+        R u1[15];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) { tr[k] = pm[(i * LPE + k) * FS + f]; zero9[k] = R(0); tb[k] = R(0); ob[k] = R(0); }
+        for (int k = 0; k < 15; ++k) u1[k] = ua[k] + ub[k];
+        R* const pmp = lds + pe * L::REGION;             // the trace area of element pe
+        R tr[9], zero9[9], tb[9], ob[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { tr[k] = pmp[(i * LPE + k) * FS + f]; zero9[k] = R(0); tb[k] = R(0); ob[k] = R(0); }
         if (!b2phase) {
-          // own flux: the element's trace is the inside state
-#pragma unroll
-          for (int k = 0; k < 7; ++k) pb[k] = R(0);
-          const R zpp = bc == 0 ? fpv[4] : zp, zsp = bc == 0 ? fpv[5] : zs;
-          godunov_adj<R>(u0, tr, zero9, fpv[0], fpv[1], fpv[2], zp, zs, zpp, zsp, lam, mu, rho_inv, fpv[3], bc, tb, ob, pb);
-#pragma unroll
-          for (int k = 0; k < 5; ++k) own5[k] += pb[k];
-          if (valid) {
-            gadd(gs, bc == 0 ? 11 + 2 * i : 3, pb[5]);
-            gadd(gs, bc == 0 ? 12 + 2 * i : 4, pb[6]);
-          }
+          // own flux: the element's trace is the inside state; its
+          // (rho_inv, lam, mu, Zp, Zs) are ev
+          const R zpp = bc == 0 ? fpv[4] : ev[3], zsp = bc == 0 ? fpv[5] : ev[4];
+          godunov_adj<R>(u0, tr, zero9, fpv[0], fpv[1], fpv[2], ev[3], ev[4], zpp, zsp, ev[1], ev[2], ev[0], fpv[3], bc,
+                         tb, ob, pbo);
         }
         if (nflux) {
           // the neighbour's flux reads this element's buffer: B1 (+ B3) or B2
           if (M == 0)
 #pragma unroll
             for (int k = 9; k < 15; ++k) u1[k] = R(0);
-#pragma unroll
-          for (int k = 0; k < 7; ++k) pb[k] = R(0);
           // (rho_inv, lam, mu, Zp, Zs) of the neighbour are its words 9..13
           godunov_adj<R>(u1, zero9, tr, fnv[0], fnv[1], fnv[2], pnv[3], pnv[4], fnv[4], fnv[5], pnv[1], pnv[2], pnv[0],
-                         fnv[3], 0, ob, tb, pb);
-#pragma unroll
-          for (int k = 0; k < 7; ++k) gadd(gs, 19 + 7 * i + k, pb[k]);
+                         fnv[3], 0, ob, tb, pbn);
         }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) pm[(i * LPE + k) * FS + f] = tb[k];
+        for (int k = 0; k < 9; ++k) pmp[(i * LPE + k) * FS + f] = tb[k];
+      }
+      // the row sums, every lane taking part (uniform control flow)
+      R so[7], sn[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) { so[k] = row_sum16(pbo[k]); sn[k] = row_sum16(pbn[k]); }
+      if (f == 15 && pvalid) {
+        double* const gp = gsh + pe * NGS;
+        if (!b2phase) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) gadd(gp, k, so[k]);
+          gadd(gp, bc == 0 ? 11 + 2 * i : 3, so[5]);
+          gadd(gp, bc == 0 ? 12 + 2 * i : 4, so[6]);
+        }
+        if (nflux)
+#pragma unroll
+          for (int k = 0; k < 7; ++k) gadd(gp, 19 + 7 * i + k, sn[k]);
       }
     }
-    if (!b2phase && valid)
-#pragma unroll
-      for (int k = 0; k < 5; ++k) gadd(gs, k, own5[k]);
     __syncthreads();
     {
       R pf[4 * FP];
@@ -1276,7 +1357,15 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int f = 0; f < FP; ++f) pf[i * FP + f] = pm[(i * LPE + q) * FS + f];
-      if (w == 0) RF::lift_p0(pf, acc); else RF::lift_p1(pf, acc);
+      // lifted into a fresh array, then added: accumulating into acc inside
+      // the two branches lets the compiler merge their first accesses through
+      // a pointer select, which keeps two entries of acc in scratch memory
+      R lr[NBX];
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) lr[lb] = R(0);
+      if (w == 0) RF::lift_p0(pf, lr); else RF::lift_p1(pf, lr);
+#pragma unroll
+      for (int lb = 0; lb < NBX; ++lb) acc[lb] += lr[lb];
     }
     __syncthreads();
   };
@@ -1430,7 +1519,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   R* const recDb = reinterpret_cast<R*>(ad.recDb);
 #pragma unroll 1
   for (int d = O - 1; d >= 0; --d) {
-    asm volatile("" : "+v"(slot), "+v"(jb0));
+    asm volatile("" : "+v"(slot), "+v"(jb0), "+s"(base));
     const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
     const bool more = d + 1 < O;
     R cur[NBX];
@@ -1541,24 +1630,56 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb) nbe[lb] = cur[lb];
   }
+  // Qbar += the adjoint of D_0: every load first, then every store (a
+  // read-modify-write per word would wait one memory latency per word: the
+  // compiler must assume each store may alias the next load)
   if (valid) {
+    R xe[NBX], xa[JW][MM][6], xd[JW][MM][6];
 #pragma unroll
-    for (int lb = 0; lb < NBX; ++lb)
-      if (lb < nb) at(Le, (base + lb) * NSLOT + slot) += nbe[lb];
+    for (int lb = 0; lb < NBX; ++lb) xe[lb] = lb < nb ? at(Le, (base + lb) * NSLOT + slot) : R(0);
     if (M > 0)
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
-        const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
+        const int lb = q + LPE * jw, jb = jb0 + jw;
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            xa[jw][l][c] = lb < nb ? la_at(jb, l, c) : R(0);
+            xd[jw][l][c] = lb < nb ? da_at(0, jb, l, c) : R(0);
+          }
+      }
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb)
+      if (lb < nb) at(Le, (base + lb) * NSLOT + slot) = xe[lb] + nbe[lb];
+    if (M > 0)
+#pragma unroll
+      for (int jw = 0; jw < JW; ++jw) {
+        const int lb = q + LPE * jw, jb = jb0 + jw;
         if (lb < nb)
 #pragma unroll
           for (int l = 0; l < MM; ++l)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) la_at(jb, l, c) += da_at(0, jb, l, c);
+            for (int c = 0; c < 6; ++c) la_at(jb, l, c) = xa[jw][l][c] + xd[jw][l][c];
       }
   }
   __syncthreads();
-  if (valid && w == 0)
-    for (int i = q; i < NG; i += LPE) ad.gacc[(size_t)elem * NG + i] += gsh[ec * NG + i];
+  // the element's gradient words, split between the two waves, loads first
+  if (valid) {
+    constexpr int NI = (NG + 2 * LPE - 1) / (2 * LPE);
+    double* const gg = ad.gacc + (size_t)elem * NG;
+    double x[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = q + LPE * (w + 2 * k);
+      x[k] = i < NG ? gg[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = q + LPE * (w + 2 * k);
+      if (i < NG) gg[i] = x[k] + gsh[ec * NGS + i];
+    }
+  }
 }
 
 // Chain rule from the per-element gradient words to d/d(rho, vp, vs), one
