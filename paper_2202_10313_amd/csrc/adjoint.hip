@@ -1176,9 +1176,12 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
               for (int c = 0; c < 6; ++c) coup[c * BS + b] = cp[c];
           }
         }
-        __syncthreads();
+        // the coupling rows of a mode are read by the stress rows of the
+        // wave that owns the mode
+        wave_lds_sync();
       }
-      // next derivative, own modes, into the row exchange
+      // next derivative, own modes, into the row exchange (every lane's
+      // full-row reads ended before the barrier after the products)
       {
         R nx[NBX];
 #pragma unroll
@@ -1193,7 +1196,6 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
             }
           }
         }
-        __syncthreads();
         if (act)
 #pragma unroll
           for (int lb = 0; lb < NBX; ++lb)
@@ -1419,8 +1421,10 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     }
   };
   star_grams(le, -1.0);
-  __syncthreads();
   // exchange: elastic adjoint rows, omega-weighted memory-variable adjoints
+  // (own modes: the rows and coupling rows write_gb reads are written by
+  // its own wave; the barrier below also ends every star-product read of
+  // the gradient slots before write_gb overwrites them)
   if (act)
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb)
@@ -1505,7 +1509,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         at(Dt, (base + lb) * NSLOT + slot) = lte[lb];
         at(Dt, (B + base + lb) * NSLOT + slot) = lt2[lb];
       }
-  __syncthreads();
+  // (no barrier: the reverse loop's first LDS writes are the wave's own
+  // modes of the exchange rows, which the transposed product does not read)
 
   // ---------------------------------------------- time kernel backwards
   // nbe: adjoint of the next elastic derivative (registers); the adjoint of
@@ -1555,7 +1560,6 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       }
       __syncthreads();
       star_grams(nbe, 1.0);
-      __syncthreads();
       if (act)
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
@@ -1567,7 +1571,9 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       __syncthreads();
       if (w == 0) RF::ck_grad_T_p0(gt0, gt1, gt2, G, cur);
       else RF::ck_grad_T_p1(gt0, gt1, gt2, G, cur);
-      __syncthreads();
+      // (no barrier: the coupling block below writes the wave's own modes of
+      // the exchange and coupling rows, which the transposed product does
+      // not read; the next iteration's products follow its first barrier)
     }
     if (M > 0) {
       // the coupling E: cq_d enters the volume term c_d cq_d and the next
@@ -1577,7 +1583,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
           if (lb < nb) rx[q * BS + base + lb] = c_d * at(Le, (base + lb) * NSLOT + slot) + (more ? nbe[lb] : R(0));
-      __syncthreads();
+      // the stress rows of a mode are read by its owner, in the same wave
+      wave_lds_sync();
       // the anelastic-weight words of both mode blocks, added once per step
       double gab[2 * MM];
 #pragma unroll
@@ -1625,7 +1632,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       if (valid)
 #pragma unroll
         for (int k = 0; k < 2 * MM; ++k) gadd(gs, 5 + k, gab[k]);
-      __syncthreads();
+      wave_lds_sync();
     }
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb) nbe[lb] = cur[lb];
