@@ -1002,8 +1002,11 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   const int* FI = p.FI + (size_t)elem * FI_WORDS;
   R* const Le = reinterpret_cast<R*>(ad.Le) + (size_t)g * B * NSLOT;
   R* const La = reinterpret_cast<R*>(ad.La) + (size_t)g * JB * MM * 6 * NSLOT;
-  R* const De = reinterpret_cast<R*>(ad.De) + (size_t)g * (O + ADJ_DE_EXTRA) * B * NSLOT;
-  R* const Dt = De + (size_t)O * B * NSLOT;        // time-integral adjoints (Dt elastic Δt, then Δt/2)
+  // Dg: per derivative d < O - 1 the two star-product sums of its gradients
+  // (rows 2d, 2d + 1), written by the recompute for the material pairings of
+  // the reverse loop; Dt: the time-integral adjoints (elastic Δt, then Δt/2)
+  R* const Dg = reinterpret_cast<R*>(ad.De) + (size_t)g * adj_de_rows(O) * B * NSLOT;
+  R* const Dt = Dg + (size_t)2 * (O - 1) * B * NSLOT;
   R* const Da = reinterpret_cast<R*>(ad.Da) + (size_t)g * O * JB * MM * 6 * NSLOT;
   const size_t sstride = (size_t)4 * ADJ_ROWS * FP;
 
@@ -1126,9 +1129,6 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb) { te[lb] += c_d * dv[lb]; t2[lb] += h_d * dv[lb]; }
         if (valid) {
-#pragma unroll
-          for (int lb = 0; lb < NBX; ++lb)
-            if (lb < nb) at(De, (d * B + base + lb) * NSLOT + slot) = dv[lb];
           if (M > 0)
 #pragma unroll
             for (int jw = 0; jw < JW; ++jw) {
@@ -1183,19 +1183,31 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       // next derivative, own modes, into the row exchange (every lane's
       // full-row reads ended before the barrier after the products)
       {
-        R nx[NBX];
+        R nx[NBX], sab[NBX], sde[NBX];
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb) {
           const int b = base + lb;
+          sab[lb] = R(0);
+          sde[lb] = R(0);
           if (lb < nb) {
+            sab[lb] = grad[sa + b] + grad[sb + b] + grad[sc + b];
             if (is_stress) {
               const R cq = M > 0 ? coup[q * BS + b] : R(0);
-              nx[lb] = lam * delta * (grad[sa + b] + grad[sb + b] + grad[sc + b]) + mu * (grad[sd + b] + grad[se + b]) + cq;
+              sde[lb] = grad[sd + b] + grad[se + b];
+              nx[lb] = lam * delta * sab[lb] + mu * sde[lb] + cq;
             } else {
-              nx[lb] = rho_inv * (grad[sa + b] + grad[sb + b] + grad[sc + b]);
+              nx[lb] = rho_inv * sab[lb];
             }
           }
         }
+        // the sums the reverse loop pairs with the adjoint of D_{d+1}
+        if (valid)
+#pragma unroll
+          for (int lb = 0; lb < NBX; ++lb)
+            if (lb < nb) {
+              at(Dg, (2 * d * B + base + lb) * NSLOT + slot) = sab[lb];
+              at(Dg, ((2 * d + 1) * B + base + lb) * NSLOT + slot) = sde[lb];
+            }
         if (act)
 #pragma unroll
           for (int lb = 0; lb < NBX; ++lb)
@@ -1396,21 +1408,14 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     for (int b = q; b < BS; b += LPE) grad[19 * BS + b] = R(0);
   __syncthreads();
   // star-product adjoint pairings with the forward gradients: dV/dlam, dV/dmu, dV/drho_inv
-  auto star_grams = [&](const R* ad_own, const double sign) {
+  auto star_sums = [&](const R* ad_own, const R* ab, const R* de, const double sign) {
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) {
-      const int b = base + lb;
+    for (int lb = 0; lb < NBX; ++lb)
       if (lb < nb) {
-        const R abc = grad[sa + b] + grad[sb + b] + grad[sc + b];
-        if (is_stress) {
-          s0 += (double)(ad_own[lb] * abc);
-          s1 += (double)(ad_own[lb] * (grad[sd + b] + grad[se + b]));
-        } else {
-          s0 += (double)(ad_own[lb] * abc);
-        }
+        s0 += (double)(ad_own[lb] * ab[lb]);
+        if (is_stress) s1 += (double)(ad_own[lb] * de[lb]);
       }
-    }
     if (valid) {
       if (is_stress) {
         if (q < 3) gadd(gs, 1, sign * s0);
@@ -1419,6 +1424,21 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         gadd(gs, 0, sign * s0);
       }
     }
+  };
+  // the same pairing with the sums read from the gradient slots
+  auto star_grams = [&](const R* ad_own, const double sign) {
+    R ab[NBX], de[NBX];
+#pragma unroll
+    for (int lb = 0; lb < NBX; ++lb) {
+      const int b = base + lb;
+      ab[lb] = R(0);
+      de[lb] = R(0);
+      if (lb < nb) {
+        ab[lb] = grad[sa + b] + grad[sb + b] + grad[sc + b];
+        if (is_stress) de[lb] = grad[sd + b] + grad[se + b];
+      }
+    }
+    star_sums(ad_own, ab, de, sign);
   };
   star_grams(le, -1.0);
   // exchange: elastic adjoint rows, omega-weighted memory-variable adjoints
@@ -1545,21 +1565,17 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         if (lb < nb) { cur[lb] += rd[lb]; rd[lb] = R(0); }
     }
     if (more) {
-      // forward gradients of D_d for the material pairings
-      if (act)
-#pragma unroll
-        for (int lb = 0; lb < NBX; ++lb)
-          if (lb < nb) rx[q * BS + base + lb] = at(De, (d * B + base + lb) * NSLOT + slot);
-      __syncthreads();
+      // material pairings with the gradients of D_d: their star-product
+      // sums were kept by the recompute
       {
-        R full[B];
+        R ab[NBX], de[NBX];
 #pragma unroll
-        for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
-        if (w == 0) RF::ck_grad_p0(full, G, gw0, gw1, gw2);
-        else RF::ck_grad_p1(full, G, gw0, gw1, gw2);
+        for (int lb = 0; lb < NBX; ++lb) {
+          ab[lb] = lb < nb ? at(Dg, (2 * d * B + base + lb) * NSLOT + slot) : R(0);
+          de[lb] = (lb < nb && is_stress) ? at(Dg, ((2 * d + 1) * B + base + lb) * NSLOT + slot) : R(0);
+        }
+        star_sums(nbe, ab, de, 1.0);
       }
-      __syncthreads();
-      star_grams(nbe, 1.0);
       if (act)
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)

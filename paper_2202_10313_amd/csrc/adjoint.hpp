@@ -15,7 +15,10 @@ constexpr int ADJ_ROWS = 15;         // adjoint face rows: 9 elastic + 6 omega-w
 //   [19+7f+0..6]      (1/rho, lam, mu, Zp, Zs, Zp+, Zs+) of the flux of the
 //                     element across face f (its neighbour-data part)
 constexpr int NG = 48;
-constexpr int ADJ_DE_EXTRA = 2;      // rows of B per element group after the derivatives in De
+// rows of B per element group in De: the one-wave kernel keeps the O time
+// derivatives there; the two-wave kernel the 2 (O - 1) star-product sums of
+// the derivatives' gradients and the 2 time-integral adjoint rows
+__host__ __device__ constexpr int adj_de_rows(int O) { return 2 * O > O + 2 ? 2 * O : O + 2; }
 
 struct APtrs {
   void* Le;          // adjoint of the elastic rows (Qe layout)
@@ -26,8 +29,7 @@ struct APtrs {
   void* S1;          // [Kp][4][15][FP] adjoint face data for the element's B1 (per own face)
   void* S2;          // [N2][4][15][FP] for B2
   void* S3;          // [N3][4][15][FP] for B3
-  void* De;          // scratch: time derivatives [G][O + ADJ_DE_EXTRA][B][63] (the two-wave kernel
-                     // keeps the time-integral adjoints of the elastic rows in the last two)
+  void* De;          // scratch: [G][adj_de_rows(O)][B][63] (see adj_de_rows)
   void* Da;          // scratch: [G][O][JB][m][6][63]
   double* gacc;      // [Kp][NG]
   void* recDb;       // [slots][O][9][B] adjoint of the receiver derivatives
