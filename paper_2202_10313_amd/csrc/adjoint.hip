@@ -945,6 +945,48 @@ struct AdjLds2 {
   static constexpr int TOTAL = EPW * REGION;
 };
 
+// Per-wave scratch of the two-wave kernel, in float4 chunks that hold four
+// consecutive values of one lane, 64 lanes side by side: an access is one
+// coalesced 1 KB transfer per instruction instead of four dword ones.  An
+// elastic block (a wave's modes of one row, NBX values) takes CE chunks, a
+// memory-variable block (one owned mode's l * 6 + c, 6 MM values) CA.
+template <int O, int M>
+struct AdjScratch2 {
+  using RF = edg_gen::Ref<O>;
+  static constexpr int NB0 = RF::MB1, NB1 = RF::B - RF::MB1;
+  static constexpr int NBX = NB0 > NB1 ? NB0 : NB1;
+  static constexpr int JW = (NBX + LPE - 1) / LPE;
+  static constexpr int MM = M > 0 ? M : 1;
+  static constexpr int CE = (NBX + 3) / 4, CA = (6 * MM + 3) / 4;
+  static constexpr int DA = 0;                       // [O][JW] forward D_d^a, then its adjoint
+  static constexpr int DG = DA + O * JW * CA;        // [O - 1][2] star-product sums of grad D_d
+  static constexpr int DT = DG + (O - 1) * 2 * CE;   // [2] time-integral adjoints (Δt, Δt/2)
+  static constexpr int LE = DT + 2 * CE;             // Qbar's elastic rows (own modes)
+  static constexpr int LA = LE + CE;                 // [JW] Qbar's memory variables
+  static constexpr int CHUNKS = LA + JW * CA;
+  static constexpr int WAVE_FLOATS = CHUNKS * 64 * 4;
+};
+template <int N>
+__device__ __forceinline__ void st_chunks(float* base, int l4, const float* v) {
+#pragma unroll
+  for (int k = 0; k < (N + 3) / 4; ++k) {
+    const float4 x = make_float4(v[4 * k], 4 * k + 1 < N ? v[4 * k + 1] : 0.f, 4 * k + 2 < N ? v[4 * k + 2] : 0.f,
+                                 4 * k + 3 < N ? v[4 * k + 3] : 0.f);
+    *reinterpret_cast<float4*>(base + k * 256 + l4) = x;
+  }
+}
+template <int N>
+__device__ __forceinline__ void ld_chunks(const float* base, int l4, float* v) {
+#pragma unroll
+  for (int k = 0; k < (N + 3) / 4; ++k) {
+    const float4 x = *reinterpret_cast<const float4*>(base + k * 256 + l4);
+    v[4 * k] = x.x;
+    if (4 * k + 1 < N) v[4 * k + 1] = x.y;
+    if (4 * k + 2 < N) v[4 * k + 2] = x.z;
+    if (4 * k + 3 < N) v[4 * k + 3] = x.w;
+  }
+}
+
 // (row, direction) -> gradient slot: velocity rows all directions, stress row
 // (i, j) directions i and j; 18 = not read, 19 = zeros
 __device__ __forceinline__ int aslot(int row, int dir) {
@@ -1002,12 +1044,15 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   const int* FI = p.FI + (size_t)elem * FI_WORDS;
   R* const Le = reinterpret_cast<R*>(ad.Le) + (size_t)g * B * NSLOT;
   R* const La = reinterpret_cast<R*>(ad.La) + (size_t)g * JB * MM * 6 * NSLOT;
-  // Dg: per derivative d < O - 1 the two star-product sums of its gradients
-  // (rows 2d, 2d + 1), written by the recompute for the material pairings of
-  // the reverse loop; Dt: the time-integral adjoints (elastic Δt, then Δt/2)
-  R* const Dg = reinterpret_cast<R*>(ad.De) + (size_t)g * adj_de_rows(O) * B * NSLOT;
-  R* const Dt = Dg + (size_t)2 * (O - 1) * B * NSLOT;
-  R* const Da = reinterpret_cast<R*>(ad.Da) + (size_t)g * O * JB * MM * 6 * NSLOT;
+  // the wave's scratch block (AdjScratch2) and this lane's offset in a chunk
+  using SC = AdjScratch2<O, M>;
+  static_assert(sizeof(R) == 4, "float4 scratch chunks");
+  float* const SW = reinterpret_cast<float*>(ad.De) + ((size_t)g * 2 + w) * SC::WAVE_FLOATS;
+  int l4 = lane * 4;                               // re-declared opaque at the loop tops (see slot)
+  auto stE = [&](int chunk, const R* v) { st_chunks<NBX>(SW + chunk * 256, l4, v); };
+  auto ldE = [&](int chunk, R* v) { ld_chunks<NBX>(SW + chunk * 256, l4, v); };
+  auto stA = [&](int chunk, const R* v) { st_chunks<6 * MM>(SW + chunk * 256, l4, v); };
+  auto ldA = [&](int chunk, R* v) { ld_chunks<6 * MM>(SW + chunk * 256, l4, v); };
   const size_t sstride = (size_t)4 * ADJ_ROWS * FP;
 
   const bool is_stress = q < 6;
@@ -1118,7 +1163,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     }
 #pragma unroll 1
     for (int d = 0; d < O; ++d) {
-      asm volatile("" : "+v"(slot), "+v"(jb0), "+s"(base));
+      asm volatile("" : "+v"(slot), "+v"(jb0), "+s"(base), "+v"(l4));
       const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
       const bool more = d + 1 < O;
       __syncthreads();
@@ -1128,18 +1173,9 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         for (int lb = 0; lb < NBX; ++lb) dv[lb] = lb < nb ? rx[q * BS + base + lb] : R(0);
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb) { te[lb] += c_d * dv[lb]; t2[lb] += h_d * dv[lb]; }
-        if (valid) {
-          if (M > 0)
+        if (M > 0)
 #pragma unroll
-            for (int jw = 0; jw < JW; ++jw) {
-              const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
-              if (lb < nb)
-#pragma unroll
-                for (int l = 0; l < MM; ++l)
-#pragma unroll
-                  for (int c = 0; c < 6; ++c) at(Da, (((d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot) = dm[jw][l][c];
-            }
-        }
+          for (int jw = 0; jw < JW; ++jw) stA(SC::DA + (d * JW + jw) * SC::CA, &dm[jw][0][0]);
       }
       if (!more) break;
       {
@@ -1201,13 +1237,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
           }
         }
         // the sums the reverse loop pairs with the adjoint of D_{d+1}
-        if (valid)
-#pragma unroll
-          for (int lb = 0; lb < NBX; ++lb)
-            if (lb < nb) {
-              at(Dg, (2 * d * B + base + lb) * NSLOT + slot) = sab[lb];
-              at(Dg, ((2 * d + 1) * B + base + lb) * NSLOT + slot) = sde[lb];
-            }
+        stE(SC::DG + (d * 2 + 0) * SC::CE, sab);
+        stE(SC::DG + (d * 2 + 1) * SC::CE, sde);
         if (act)
 #pragma unroll
           for (int lb = 0; lb < NBX; ++lb)
@@ -1391,6 +1422,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   R le[NBX];
 #pragma unroll
   for (int lb = 0; lb < NBX; ++lb) le[lb] = lb < nb ? at(Le, (base + lb) * NSLOT + slot) : R(0);
+  stE(SC::LE, le);                                 // for the reverse loop's coupling blocks
   auto la_at = [&](int jb, int l, int c) -> R& { return at(La, ((jb * MM + l) * 6 + c) * NSLOT + slot); };
   if (act)
 #pragma unroll
@@ -1453,12 +1485,18 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
     for (int jw = 0; jw < JW; ++jw) {
       const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
+      R lv[6 * MM];
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) lv[l * 6 + c] = lb < nb ? la_at(jb, l, c) : R(0);
+      stA(SC::LA + jw * SC::CA, lv);               // for the reverse loop's coupling blocks
       if (lb < nb && act)
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
           R v = R(0);
 #pragma unroll
-          for (int l = 0; l < MM; ++l) v += om[l] * la_at(jb, l, c);
+          for (int l = 0; l < MM; ++l) v += om[l] * lv[l * 6 + c];
           coup[c * BS + b] = v;
         }
     }
@@ -1522,13 +1560,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   else RF::vol_grad_T_p1(gt0, gt1, gt2, G, lte);
   // the time-integral adjoints wait in memory (re-read with each
   // derivative's data), so they hold no registers across the loop below
-  if (act)
-#pragma unroll
-    for (int lb = 0; lb < NBX; ++lb)
-      if (lb < nb) {
-        at(Dt, (base + lb) * NSLOT + slot) = lte[lb];
-        at(Dt, (B + base + lb) * NSLOT + slot) = lt2[lb];
-      }
+  stE(SC::DT, lte);
+  stE(SC::DT + SC::CE, lt2);
   // (no barrier: the reverse loop's first LDS writes are the wave's own
   // modes of the exchange rows, which the transposed product does not read)
 
@@ -1540,21 +1573,19 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   R nbe[NBX];
 #pragma unroll
   for (int lb = 0; lb < NBX; ++lb) nbe[lb] = R(0);
-  auto da_at = [&](int d, int jb, int l, int c) -> R& { return at(Da, (((d * JB + jb) * MM + l) * 6 + c) * NSLOT + slot); };
   R* const recDb = reinterpret_cast<R*>(ad.recDb);
 #pragma unroll 1
   for (int d = O - 1; d >= 0; --d) {
-    asm volatile("" : "+v"(slot), "+v"(jb0), "+s"(base));
+    asm volatile("" : "+v"(slot), "+v"(jb0), "+s"(base), "+v"(l4));
     const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
     const bool more = d + 1 < O;
     R cur[NBX];
     {
       R x1[NBX], x2[NBX];
 #pragma unroll
-      for (int lb = 0; lb < NBX; ++lb) {
-        x1[lb] = lb < nb ? at(Dt, (base + lb) * NSLOT + slot) : R(0);
-        x2[lb] = lb < nb ? at(Dt, (B + base + lb) * NSLOT + slot) : R(0);
-      }
+      for (int lb = 0; lb < NBX; ++lb) { x1[lb] = R(0); x2[lb] = R(0); }
+      ldE(SC::DT, x1);
+      ldE(SC::DT + SC::CE, x2);
 #pragma unroll
       for (int lb = 0; lb < NBX; ++lb) cur[lb] = c_d * x1[lb] + h_d * x2[lb];
     }
@@ -1569,11 +1600,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       // sums were kept by the recompute
       {
         R ab[NBX], de[NBX];
-#pragma unroll
-        for (int lb = 0; lb < NBX; ++lb) {
-          ab[lb] = lb < nb ? at(Dg, (2 * d * B + base + lb) * NSLOT + slot) : R(0);
-          de[lb] = (lb < nb && is_stress) ? at(Dg, ((2 * d + 1) * B + base + lb) * NSLOT + slot) : R(0);
-        }
+        ldE(SC::DG + (2 * d) * SC::CE, ab);
+        ldE(SC::DG + (2 * d + 1) * SC::CE, de);
         star_sums(nbe, ab, de, 1.0);
       }
       if (act)
@@ -1595,10 +1623,13 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       // the coupling E: cq_d enters the volume term c_d cq_d and the next
       // derivative.  The global operands of a mode block (forward D_d, the
       // carried adjoint, Qbar's memory variables) are loaded in one batch.
-      if (is_stress && act)
+      if (is_stress && act) {
+        R lev[NBX];
+        ldE(SC::LE, lev);
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
-          if (lb < nb) rx[q * BS + base + lb] = c_d * at(Le, (base + lb) * NSLOT + slot) + (more ? nbe[lb] : R(0));
+          if (lb < nb) rx[q * BS + base + lb] = c_d * lev[lb] + (more ? nbe[lb] : R(0));
+      }
       // the stress rows of a mode are read by its owner, in the same wave
       wave_lds_sync();
       // the anelastic-weight words of both mode blocks, added once per step
@@ -1610,19 +1641,19 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
         if (lb < nb) {
           R dmd[MM][6], nxt[MM][6], lav[MM][6];
+          ldA(SC::DA + (d * JW + jw) * SC::CA, &dmd[0][0]);
 #pragma unroll
           for (int l = 0; l < MM; ++l)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-              dmd[l][c] = da_at(d, jb, l, c);
-              nxt[l][c] = more ? da_at(d + 1, jb, l, c) : R(0);
-              lav[l][c] = la_at(jb, l, c);
-            }
+            for (int c = 0; c < 6; ++c) nxt[l][c] = R(0);
+          if (more) ldA(SC::DA + ((d + 1) * JW + jw) * SC::CA, &nxt[0][0]);
+          ldA(SC::LA + jw * SC::CA, &lav[0][0]);
           R cqb[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) cqb[c] = rx[c * BS + b];
           const R cqt = cqb[0] + cqb[1] + cqb[2];
           R ws[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+          R vv[MM][6];
 #pragma unroll
           for (int l = 0; l < MM; ++l) {
             const R tr = dmd[l][0] + dmd[l][1] + dmd[l][2];
@@ -1634,10 +1665,12 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
               const R v = -om[l] * (c_d * lav[l][c] + nxt[l][c]) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
-              if (act) da_at(d, jb, l, c) = v;
+              vv[l][c] = v;
               ws[c] += om[l] * v;
             }
           }
+          // the adjoint of D_d^a replaces D_d^a (the next step reads it)
+          stA(SC::DA + (d * JW + jw) * SC::CA, &vv[0][0]);
           // the coupling term of the next (lower) derivative's adjoint: coup
           // is not touched again before the next step reads it
           if (act)
@@ -1659,18 +1692,13 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   if (valid) {
     R xe[NBX], xa[JW][MM][6], xd[JW][MM][6];
 #pragma unroll
-    for (int lb = 0; lb < NBX; ++lb) xe[lb] = lb < nb ? at(Le, (base + lb) * NSLOT + slot) : R(0);
+    for (int lb = 0; lb < NBX; ++lb) xe[lb] = R(0);
+    ldE(SC::LE, xe);                               // Qbar as staged (unchanged until here)
     if (M > 0)
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
-        const int lb = q + LPE * jw, jb = jb0 + jw;
-#pragma unroll
-        for (int l = 0; l < MM; ++l)
-#pragma unroll
-          for (int c = 0; c < 6; ++c) {
-            xa[jw][l][c] = lb < nb ? la_at(jb, l, c) : R(0);
-            xd[jw][l][c] = lb < nb ? da_at(0, jb, l, c) : R(0);
-          }
+        ldA(SC::LA + jw * SC::CA, &xa[jw][0][0]);
+        ldA(SC::DA + jw * SC::CA, &xd[jw][0][0]);
       }
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb)
@@ -1812,6 +1840,12 @@ int launch_adjoint(const KPtrs& p, const APtrs& ad, const LevelArgs& a, hipStrea
 }
 
 template <class R, int O, int M>
+size_t adjoint_scratch_floats() {
+  if constexpr (std::is_same<R, float>::value && O >= 4) return (size_t)2 * AdjScratch2<O, M>::WAVE_FLOATS;
+  else return (size_t)O * edg_gen::Ref<O>::B * NSLOT;   // the one-wave kernel's time derivatives
+}
+
+template <class R, int O, int M>
 int launch_receivers_adj(const KPtrs& p, const APtrs& ad, const LevelArgs& a, const RecArgs& r, const double* seis_b,
                          hipStream_t st) {
   if (r.n <= 0) return 0;
@@ -1830,6 +1864,7 @@ int launch_material_gradient(const double* gacc, const int* FI, const double* ma
 
 #define EDG_ADJ_INST(R, O, M)                                                                    \
   template int launch_adjoint<R, O, M>(const KPtrs&, const APtrs&, const LevelArgs&, hipStream_t); \
+  template size_t adjoint_scratch_floats<R, O, M>();                                              \
   template int launch_receivers_adj<R, O, M>(const KPtrs&, const APtrs&, const LevelArgs&, const RecArgs&, \
                                              const double*, hipStream_t);
 

@@ -15,10 +15,6 @@ constexpr int ADJ_ROWS = 15;         // adjoint face rows: 9 elastic + 6 omega-w
 //   [19+7f+0..6]      (1/rho, lam, mu, Zp, Zs, Zp+, Zs+) of the flux of the
 //                     element across face f (its neighbour-data part)
 constexpr int NG = 48;
-// rows of B per element group in De: the one-wave kernel keeps the O time
-// derivatives there; the two-wave kernel the 2 (O - 1) star-product sums of
-// the derivatives' gradients and the 2 time-integral adjoint rows
-__host__ __device__ constexpr int adj_de_rows(int O) { return 2 * O > O + 2 ? 2 * O : O + 2; }
 
 struct APtrs {
   void* Le;          // adjoint of the elastic rows (Qe layout)
@@ -29,7 +25,7 @@ struct APtrs {
   void* S1;          // [Kp][4][15][FP] adjoint face data for the element's B1 (per own face)
   void* S2;          // [N2][4][15][FP] for B2
   void* S3;          // [N3][4][15][FP] for B3
-  void* De;          // scratch: [G][adj_de_rows(O)][B][63] (see adj_de_rows)
+  void* De;          // scratch: adjoint_scratch_floats() words per element group
   void* Da;          // scratch: [G][O][JB][m][6][63]
   double* gacc;      // [Kp][NG]
   void* recDb;       // [slots][O][9][B] adjoint of the receiver derivatives
@@ -42,6 +38,9 @@ int launch_material_gradient(const double* gacc, const int* FI, const double* ma
 
 template <class R, int O, int M>
 int launch_adjoint(const KPtrs& p, const APtrs& ad, const LevelArgs& a, hipStream_t st);
+// words of De per element group for the transposed prediction of this variant
+template <class R, int O, int M>
+size_t adjoint_scratch_floats();
 template <class R, int O, int M>
 int launch_receivers_adj(const KPtrs& p, const APtrs& ad, const LevelArgs& a, const RecArgs& r, const double* seis_b,
                          hipStream_t st);

@@ -1689,7 +1689,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
       (rc = dev_reserve(c, c->aS1, (size_t)c->Kp * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS2, (size_t)c->N2 * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS3, (size_t)c->N3 * slot_words * rs)) ||
-      (rc = dev_reserve(c, c->aDe, (size_t)c->G * adj_de_rows(O) * B * EPW * LPE * rs)) ||
+      (rc = dev_reserve(c, c->aDe, (size_t)c->G * adjoint_scratch_floats<R, O, M>() * rs)) ||
       (rc = dev_reserve(c, c->aDa, std::max<size_t>((size_t)c->G * O * JB * M * 6 * EPW * LPE, 1) * rs)) ||
       (rc = dev_reserve(c, c->agacc, (size_t)c->Kp * NG * sizeof(double))) ||
       (rc = dev_reserve(c, c->arecDb, std::max<size_t>(c->run_recd, 1) * rs)) ||
