@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--c5-seconds", type=float, default=4.0, help="simulated time of the gradient line")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch every level eagerly")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false", help="keep the default launch plan")
+    ap.add_argument("--trace-mfma", action="store_true",
+                    help="form the traces of faces 0 and 1 on the matrix cores (launch-plan option trace_mfma)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (profiler calibration of FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -262,6 +264,9 @@ def main():
         total_t = (warmup + steps + 16) * sync
         ctx.set_receivers(rec, 0.005, int(total_t / 0.005) + 2)
         plan, tuned_ms = ctx.autotune(cycles=1) if args.autotune else (ctx.get_plan(), None)
+        if args.trace_mfma:
+            plan = dict(plan, trace_mfma=1)
+            ctx.set_plan(**plan)
         print(f"[bench] launch plan {plan} ({tuned_ms} ms per cycle while tuning)", file=sys.stderr, flush=True)
         t_start = ctx.time()
         ctx.advance_to(t_start + warmup * sync)

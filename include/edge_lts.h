@@ -84,12 +84,15 @@ typedef struct {
                               captured HIP graph (kernel nodes only; recaptured after a change of
                               sources, receivers, clusters or launch plan) */
 
-/* Launch plan of the element-update kernel.  Every plan gives bit-identical
- * results; only the speed differs. */
+/* Launch plan of the element-update kernel.  Every plan but trace_mfma gives
+ * bit-identical results; only the speed differs. */
 typedef struct {
   int32_t xcd_remap;  /* 1: the workgroups dealt to one XCD take a contiguous range of element
                          groups (neighbour traces then stay in that XCD's L2) */
   int32_t run_chunk;  /* runs per launch (0 = all runs in one launch) */
+  int32_t trace_mfma; /* 1: the traces of faces 0 and 1 as one dense product on the matrix cores
+                         (two-wave FP32 kernel, orders 4 and 5; elsewhere ignored).  Results
+                         agree with the vector-ALU traces to FP32 rounding, not bit for bit. */
 } edg_plan;
 
 /* Create a context on cfg->device.  *out receives the handle (NULL on

@@ -38,10 +38,10 @@ class EdgError(RuntimeError):
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("xcd_remap", ctypes.c_int32), ("run_chunk", ctypes.c_int32)]
+    _fields_ = [("xcd_remap", ctypes.c_int32), ("run_chunk", ctypes.c_int32), ("trace_mfma", ctypes.c_int32)]
 
     def as_dict(self):
-        return dict(xcd_remap=self.xcd_remap, run_chunk=self.run_chunk)
+        return dict(xcd_remap=self.xcd_remap, run_chunk=self.run_chunk, trace_mfma=self.trace_mfma)
 
 
 class Config(ctypes.Structure):
@@ -272,8 +272,8 @@ class Context:
     def element_updates(self):
         return self._L.edg_element_updates(self.h)
 
-    def set_plan(self, xcd_remap=0, run_chunk=0):
-        pl = Plan(int(xcd_remap), int(run_chunk))
+    def set_plan(self, xcd_remap=0, run_chunk=0, trace_mfma=0):
+        pl = Plan(int(xcd_remap), int(run_chunk), int(trace_mfma))
         self._chk(self._L.edg_set_plan(self.h, ctypes.byref(pl)))
 
     def get_plan(self):

@@ -698,6 +698,7 @@ LevelArgs base_args(const edg_ctx* c) {
   for (int l = 0; l < c->M; ++l) a.omega[l] = c->omega[l];
   a.clock = (const long long*)c->dclock.p;
   a.xcd_remap = c->plan.xcd_remap;
+  a.trace_mfma = c->plan.trace_mfma;
   return a;
 }
 
@@ -1570,7 +1571,8 @@ int edg_advance_to(edg_ctx* c, double t) {
 
 int edg_set_plan(edg_ctx* c, const edg_plan* plan) {
   if (!c) return EDG_EINVAL;
-  if (!plan || (plan->xcd_remap != 0 && plan->xcd_remap != 1) || plan->run_chunk < 0 || plan->run_chunk > MAX_RUNS)
+  if (!plan || (plan->xcd_remap != 0 && plan->xcd_remap != 1) || plan->run_chunk < 0 || plan->run_chunk > MAX_RUNS ||
+      (plan->trace_mfma != 0 && plan->trace_mfma != 1))
     return fail(c, EDG_EINVAL, "bad launch plan");
   c->plan = *plan;
   drop_graph(c);

@@ -504,8 +504,10 @@ __device__ __forceinline__ int gslot(int row, int dir) {
 
 // KIND is the launch kind (KIND_PREDICT, KIND_FUSED, KIND_NEIGHBOR) as a
 // template parameter: one code path per kernel keeps the register allocation
-// of the fused path free of the neighbour-only exit.
-template <class R, int O, int M, int KIND>
+// of the fused path free of the neighbour-only exit.  TM: the traces of faces
+// 0 and 1 (the two densest) as one dense product on the matrix cores.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+template <class R, int O, int M, int KIND, bool TM = false>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 4)))
 void k_level2(KPtrs p, LevelArgs a) {
   using RF = edg_gen::Ref<O>;
@@ -522,6 +524,8 @@ void k_level2(KPtrs p, LevelArgs a) {
   // Godunov items of the surface phase
   __shared__ R fdat[KIND != KIND_PREDICT ? EPW * 4 * 8 : 1];
   __shared__ int fbc[KIND != KIND_PREDICT ? EPW * 4 : 1];
+  // per element: flags and own B3 slot, for the matrix-core trace's exports
+  __shared__ int tme[TM ? EPW * 2 : 1];
 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave (uniform)
   const int lane = threadIdx.x & 63;
@@ -820,6 +824,12 @@ void k_level2(KPtrs p, LevelArgs a) {
   // the time integrals, so no register copy of it is kept across the loop.
   const int nn = step_new_of(a, cl);
   const int eflags = FI[12];
+  if constexpr (TM) {
+    if (w == 0 && q == 0 && e < EPW) {
+      tme[ec * 2] = eflags;
+      tme[ec * 2 + 1] = FI[14];
+    }
+  }
   const bool need_b2 = __syncthreads_or((eflags & EF_HAS_FINER) != 0);
   const int rec_slot = FI[15];
   R te[NBX], t2[NBX];
@@ -928,6 +938,12 @@ void k_level2(KPtrs p, LevelArgs a) {
   // before the time integral is written there)
 
   // ------------------------------------------------ traces and volume
+  // (the matrix-core trace's coefficients are requested before the barrier,
+  // so their latency overlaps it)
+  float ftb[TM ? RF::MK : 1];
+  if constexpr (TM)
+#pragma unroll
+    for (int st = 0; st < RF::MK; ++st) ftb[st] = RF::FT01[st * 64 + lane];
 #pragma unroll
   for (int lb = 0; lb < NBX; ++lb)
     if (lb < nb) rx[q * BS + base + lb] = te[lb];
@@ -936,6 +952,7 @@ void k_level2(KPtrs p, LevelArgs a) {
     R full[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) full[b] = rx[q * BS + b];
+    if constexpr (!TM) {
     R pt[2 * FP];
     if (w == 0) RF::trace_p0(full, pt); else RF::trace_p1(full, pt);
     const int own = fresh(ec * TS + q * FP);
@@ -959,6 +976,60 @@ void k_level2(KPtrs p, LevelArgs a) {
 #pragma unroll
           for (int f = 0; f < FP; ++f) T3[q * FP + RF::tface(w, ii) * LPE * FP + f] += pt[ii * FP + f];
       }
+    }
+    } else {
+      // faces 0 and 1 on the matrix cores: wave w multiplies the group's rows
+      // [32 w, 32 w + 32) (row 9 e + q of the exchange; row 63 is padding) by
+      // the two faces' trace coefficients, 32 columns (face, face mode), two
+      // modes per step; its sparse face (3, or 2) stays on the vector ALUs
+      static_assert(sizeof(R) == 4 && FP <= 16, "matrix-core trace: FP32, at most 16 face modes");
+      floatx16 acc;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+      const int kh = lane >> 5;
+      const int ar = 32 * w + (lane & 31), ae = ar / LPE, aq = ar - LPE * ae;
+      const R* const arow = lds + (ae < EPW ? ae : EPW - 1) * L::REGION + L::GRAD + L::COUP + aq * BS;
+#pragma unroll
+      for (int st = 0; st < RF::MK; ++st) {
+        const int k = 2 * st + kh;
+        const float av = (ar < EPW * LPE && k < B) ? arow[k] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, ftb[st], acc, 0, 0, 0);
+      }
+      R pt[FP];
+      if (w == 0) RF::trace_f3(full, pt); else RF::trace_f2(full, pt);
+      const int fs = w == 0 ? 3 : 2;
+      R* const T1 = reinterpret_cast<R*>(p.T1) + (size_t)(nn & 1) * Kp * tstride + tg;
+      const int own = fresh(ec * TS + q * FP);
+      if (valid)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) T1[own + fs * LPE * FP + f] = pt[f];
+      if ((eflags & EF_HAS_COARSER) && valid) {
+        R* T3 = reinterpret_cast<R*>(p.T3) + ((size_t)((nn >> 1) & 1) * p.N3 + (size_t)FI[14]) * tstride;
+        if ((nn & 1) == 0) {
+#pragma unroll
+          for (int f = 0; f < FP; ++f) T3[q * FP + fs * LPE * FP + f] = pt[f];
+        } else {
+#pragma unroll
+          for (int f = 0; f < FP; ++f) T3[q * FP + fs * LPE * FP + f] += pt[f];
+        }
+      }
+      // accumulator register j holds row 32 w + 8 (j / 4) + 4 (lane / 32) +
+      // j % 4, column lane % 32 = 16 face + face mode
+      const int col = lane & 31, fc = col >> 4, ff = col & 15;
+      if (ff < FP)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int m = 32 * w + 8 * (j >> 2) + 4 * kh + (j & 3);
+          const int e2 = m / LPE, q2 = m - LPE * e2;
+          if (m < EPW * LPE && g * EPW + e2 < a.cl_vend[cl]) {
+            T1[e2 * TS + (fc * LPE + q2) * FP + ff] = acc[j];
+            if (tme[e2 * 2] & EF_HAS_COARSER) {
+              R* T3 = reinterpret_cast<R*>(p.T3) + ((size_t)((nn >> 1) & 1) * p.N3 + (size_t)tme[e2 * 2 + 1]) * tstride;
+              if ((nn & 1) == 0) T3[(fc * LPE + q2) * FP + ff] = acc[j];
+              else T3[(fc * LPE + q2) * FP + ff] += acc[j];
+            }
+          }
+        }
     }
     if (w == 0) RF::vol_grad_p0(full, G, gw0, gw1, gw2);
     else RF::vol_grad_p1(full, G, gw0, gw1, gw2);
@@ -1139,7 +1210,11 @@ int launch_level(const KPtrs& p, const LevelArgs& a, int runs, hipStream_t st) {
   if (groups <= 0 || runs <= 0) return 0;
   const dim3 grid(groups, runs);
   if constexpr (std::is_same<R, float>::value && O >= 4) {
-    if (a.kind == KIND_FUSED)
+    if (a.kind == KIND_FUSED && a.trace_mfma)
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_FUSED, true>), grid, dim3(128), 0, st, p, a);
+    else if (a.kind == KIND_PREDICT && a.trace_mfma)
+      hipLaunchKernelGGL((k_level2<R, O, M, KIND_PREDICT, true>), grid, dim3(128), 0, st, p, a);
+    else if (a.kind == KIND_FUSED)
       hipLaunchKernelGGL((k_level2<R, O, M, KIND_FUSED>), grid, dim3(128), 0, st, p, a);
     else if (a.kind == KIND_PREDICT)
       hipLaunchKernelGGL((k_level2<R, O, M, KIND_PREDICT>), grid, dim3(128), 0, st, p, a);

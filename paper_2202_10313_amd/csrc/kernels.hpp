@@ -58,6 +58,7 @@ struct LevelArgs {
   const long long* clock;
   int jrel;
   int xcd_remap;     // 1: the workgroups of one XCD take a contiguous range of element groups
+  int trace_mfma;    // 1: the traces of faces 0 and 1 on the matrix cores (two-wave FP32 kernel)
   double dt[MAX_CLUSTERS];
   double tc[MAX_CLUSTERS][MAX_ORDER];  // dt^{d+1}/(d+1)!
   double th[MAX_CLUSTERS][MAX_ORDER];  // (dt/2)^{d+1}/(d+1)!

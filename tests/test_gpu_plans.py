@@ -67,6 +67,23 @@ def test_plans_and_graph_replays_are_bit_identical():
     print("graph replays: identical")
 
 
+def test_matrix_core_traces_agree_with_the_vector_traces():
+    """The trace_mfma plan forms the traces of faces 0 and 1 on the matrix
+    cores (one dense product, other summation order): equal to the default
+    path to FP32 rounding after every advance, with its graph replays."""
+    from paper_2202_10313_amd import FLAG_GRAPH
+    w = anelastic_setup("tiny", ORDER, 3, with_source=False)
+    ref = states(configured(w))
+    for flags in (0, FLAG_GRAPH):
+        got = states(configured(w, dict(xcd_remap=1, run_chunk=0, trace_mfma=1), flags=flags))
+        for i, (sa, sb) in enumerate(zip(ref, got)):
+            for r, ((qa, ra), (qb, rb)) in enumerate(zip(sa, sb)):
+                dq = np.max(np.abs(qa - qb)) / np.max(np.abs(qa))
+                dr = np.max(np.abs(ra - rb)) / max(np.max(np.abs(ra)), 1e-30)
+                assert dq < 2e-5 and dr < 2e-5, f"flags {flags}, advance {i}, run {r}: rel. diff {dq:.2e} / {dr:.2e}"
+        print(f"trace_mfma (flags {flags}): max rel. diff within 2e-5")
+
+
 def test_autotune_keeps_the_solution():
     w = anelastic_setup("tiny", ORDER, 3, with_source=False)
     ref = configured(w)
@@ -93,3 +110,5 @@ def test_bad_plan_rejected():
         ctx.set_plan(xcd_remap=2)
     with pytest.raises(EdgError):
         ctx.set_plan(run_chunk=-1)
+    with pytest.raises(EdgError):
+        ctx.set_plan(trace_mfma=2)
