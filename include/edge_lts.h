@@ -251,11 +251,13 @@ int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cy
 /* every_cycles > 0: from now on edg_advance_to splits its cycles into
  * segments of at most every_cycles cycles and stores the state (device
  * memory, K x Nq x B words each) at the start of every segment; 0 turns it
- * off.  The final segment of each edg_advance_to call also records the state
- * at the start of every level's predictions ((levels per segment) x K x Nq x
- * B words of device memory, reused by edg_adjoint; the forward kernels write
- * it), without graph replay; its launches are not counted by the timing
- * queries.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a
+ * off.  The final segment of each edg_advance_to call also records, at every
+ * level, the state of the elements that start a step there (device memory,
+ * reused by edg_adjoint; the forward kernels write it): per LTS cycle
+ * (element updates of the cycle) x Nq x B words, 1.9 x K x Nq x B at the
+ * benchmark's three cluster sizes; an interval whose record does not fit fails
+ * with EDG_ENOMEM naming the bytes it needs.  The segment runs without graph
+ * replay; its launches are not counted by the timing queries.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a
  * negative interval.  The checkpoints are dropped again by edg_set_initial,
  * edg_set_dofs_subset, edg_upload_materials, edg_upload_clusters,
  * edg_set_sources and edg_rewind. */

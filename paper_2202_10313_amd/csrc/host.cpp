@@ -95,8 +95,8 @@ struct edg_ctx {
 
   std::vector<std::vector<double>> perm_mats;  // 24 B x B conversion matrices
 
-  // launch plan (all plans give bit-identical results) and cycle graph
-  edg_plan plan{0, 0};
+  // launch plan (all but trace_mfma give bit-identical results) and cycle graph
+  edg_plan plan{0, 0, 0};
   DevBuf dclock;                     // level at the start of the current cycle (device)
   hipGraphExec_t cycle_exec = nullptr;
   hipGraph_t cycle_graph = nullptr;
@@ -1431,13 +1431,40 @@ int store_checkpoint(edg_ctx* c) {
   return 0;
 }
 
-// ahist: one full run-0 state per level of the longest segment (levels
-// 0 .. J-1), of which the element groups that predict at a level are written
+// ahist: per level of the longest segment (levels 0 .. J-1) the run-0 state
+// of the element groups that predict there (groups [0, cl_end[lmax(j)] / 7),
+// elastic words then memory-variable words), packed level after level
+size_t hist_group_words(const edg_ctx* c) { return (c->run_qe + c->run_qa) / (size_t)c->G; }
+size_t hist_level_groups(const edg_ctx* c, int64_t j) { return (size_t)c->cl_end[level_lmax(c, j)] / EPW; }
+// words of the records of levels 0 .. j-1 (the pattern repeats every cycle)
+size_t hist_words_before(const edg_ctx* c, int64_t j) {
+  const int64_t per = (int64_t)1 << (c->cfg.n_clusters - 1);
+  size_t cyc = 0, part = 0;
+  for (int64_t i = 0; i < per; ++i) {
+    const size_t g = hist_level_groups(c, i);
+    cyc += g;
+    if (i < j % per) part += g;
+  }
+  return ((size_t)(j / per) * cyc + part) * hist_group_words(c);
+}
+char* hist_rec_e(edg_ctx* c, int64_t j) {
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  return (char*)c->ahist.p + hist_words_before(c, j) * rs;
+}
+char* hist_rec_a(edg_ctx* c, int64_t j) {
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  return hist_rec_e(c, j) + hist_level_groups(c, j) * (c->run_qe / (size_t)c->G) * rs;
+}
 int hist_reserve(edg_ctx* c, int64_t levels) {
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
-  if (c->ahist.p && c->ahist.bytes >= (size_t)levels * (c->run_qe + c->run_qa) * rs) return 0;
+  const size_t bytes = hist_words_before(c, levels) * rs;
+  if (c->ahist.p && c->ahist.bytes >= bytes) return 0;
   c->hist_valid = false;
-  return dev_reserve(c, c->ahist, (size_t)levels * (c->run_qe + c->run_qa) * rs);
+  if (dev_reserve(c, c->ahist, bytes))
+    return fail(c, EDG_ENOMEM, "the level-state record of a checkpoint segment (" + std::to_string(levels) +
+                                   " levels) needs " + std::to_string(bytes) +
+                                   " bytes of device memory: use a shorter checkpoint interval");
+  return 0;
 }
 
 // The J levels of a segment from a synchronisation point, on the state p:
@@ -1448,9 +1475,7 @@ int hist_reserve(edg_ctx* c, int64_t levels) {
 // replay stops after the last prediction (the finish is not needed).
 int run_recorded_levels(edg_ctx* c, const AdvanceArgs& A, const KPtrs& p, int64_t J, bool own) {
   const int Nc = c->cfg.n_clusters;
-  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
-  const size_t we = c->run_qe, wa = c->run_qa;
-  char* const hist = (char*)c->ahist.p;
+  const size_t wa = c->run_qa;
   auto chk = [&](int e, const char* what) {
     return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
   };
@@ -1463,8 +1488,8 @@ int run_recorded_levels(edg_ctx* c, const AdvanceArgs& A, const KPtrs& p, int64_
     a.end = c->cl_end[lmax];
     if (j > 0 && c->n_src > 0 && (rc = chk(A.fn.src(p, a, A.sa, c->stream), "source kernel"))) return rc;
     a.kind = j == 0 ? KIND_PREDICT : (j == J ? KIND_NEIGHBOR : KIND_FUSED);
-    a.rec_e = j < J ? (void*)(hist + (size_t)j * (we + wa) * rs) : nullptr;
-    a.rec_a = (j < J && wa) ? (void*)(hist + ((size_t)j * (we + wa) + we) * rs) : nullptr;
+    a.rec_e = j < J ? (void*)hist_rec_e(c, j) : nullptr;
+    a.rec_a = (j < J && wa) ? (void*)hist_rec_a(c, j) : nullptr;
     if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
     if (own && j < J && c->n_rec > 0 && (rc = chk(A.fn.rec(p, a, A.ra, c->runs, c->stream), "receiver kernel")))
       return rc;
@@ -1592,7 +1617,7 @@ int edg_autotune(edg_ctx* c, int32_t cycles, edg_plan* best_out, double* best_ms
   std::vector<edg_plan> cand;
   for (int xcd = 0; xcd <= 1; ++xcd)
     for (int chunk : {0, 16, 8, 4})
-      if (chunk == 0 || chunk < c->runs) cand.push_back(edg_plan{xcd, chunk});
+      if (chunk == 0 || chunk < c->runs) cand.push_back(edg_plan{xcd, chunk, 0});
   const bool timing = c->timing;
   const int64_t l0 = c->t_launches, u0 = c->t_updates;
   const double m0 = c->t_ms;
@@ -1673,9 +1698,11 @@ namespace {
 template <class R, int O, int M>
 int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double* g_q0, double* g_rho, double* g_vp,
                   double* g_vs, bool dev) {
-  const int Nc = c->cfg.n_clusters, B = c->B, FP = c->FP, JB = jb_count(c);
+  const int Nc = c->cfg.n_clusters, FP = c->FP, JB = jb_count(c);
   const size_t rs = sizeof(R), we = c->run_qe, wa = c->run_qa;
   const size_t slot_words = (size_t)4 * ADJ_ROWS * FP;
+  // Da is the one-wave kernel's (the two-wave kernel keeps its scratch in De)
+  const bool two_wave = std::is_same<R, float>::value && O >= 4;
   const int64_t L_end = c->level;
   const size_t nck = c->ckpts.size();
   int64_t jmax = 1;
@@ -1692,7 +1719,7 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
       (rc = dev_reserve(c, c->aS2, (size_t)c->N2 * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aS3, (size_t)c->N3 * slot_words * rs)) ||
       (rc = dev_reserve(c, c->aDe, (size_t)c->G * adjoint_scratch_floats<R, O, M>() * rs)) ||
-      (rc = dev_reserve(c, c->aDa, std::max<size_t>((size_t)c->G * O * JB * M * 6 * EPW * LPE, 1) * rs)) ||
+      (rc = dev_reserve(c, c->aDa, std::max<size_t>(two_wave ? 0 : (size_t)c->G * O * JB * M * 6 * EPW * LPE, 1) * rs)) ||
       (rc = dev_reserve(c, c->agacc, (size_t)c->Kp * NG * sizeof(double))) ||
       (rc = dev_reserve(c, c->arecDb, std::max<size_t>(c->run_recd, 1) * rs)) ||
       (rc = dev_reserve(c, c->aseis, std::max<size_t>((size_t)c->n_rec * c->rec_ns * LPE, 1) * sizeof(double))) ||
@@ -1748,9 +1775,8 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   ad.gacc = (double*)c->agacc.p;
   ad.recDb = c->arecDb.p;
   const double* seis_b = (const double*)c->aseis.p;
-  char* const hist = (char*)c->ahist.p;
-  auto hist_e = [&](int64_t j) { return (void*)(hist + (size_t)j * (we + wa) * rs); };
-  auto hist_a = [&](int64_t j) { return (void*)(hist + ((size_t)j * (we + wa) + we) * rs); };
+  auto hist_e = [&](int64_t j) { return (void*)hist_rec_e(c, j); };
+  auto hist_a = [&](int64_t j) { return (void*)hist_rec_a(c, j); };
   auto chk = [&](int e, const char* what) {
     return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
   };
