@@ -533,6 +533,9 @@ def main():
                    "cost_vs_plain_forward": (a["fwd"] + a["adj"]) / wall_plain,
                    "reverse_vs_plain_forward": a["adj"] / wall_plain,
                    "checkpoint_every_cycles": args.adjoint_steps,
+                   "regime": "one checkpoint segment over the window: the forward records every level's state and "
+                             "the sweep replays nothing (the no-replay best case; checkpoint_per_cycle replays "
+                             "every segment but the last, and c5_gradient_o4 a checkpoint every 50 cycles)",
                    "checkpoint_per_cycle": {"forward_checkpointed_ms": a1["fwd"] * 1e3,
                                             "reverse_sweep_ms": a1["adj"] * 1e3,
                                             "cost_vs_plain_forward": (a1["fwd"] + a1["adj"]) / wall_plain},
