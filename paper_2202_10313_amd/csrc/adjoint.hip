@@ -373,14 +373,17 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
     R* const S1 = reinterpret_cast<R*>(ad.S1);
     R* const S2 = reinterpret_cast<R*>(ad.S2);
     R* const S3 = reinterpret_cast<R*>(ad.S3);
-    auto scatter = [&](const R* u, int i, int row) {
+    // one face row's adjoints u to S0 and, added (or subtracted for -B2), to
+    // the slot the neighbour across face i keeps for the buffer it read; the
+    // face words (neighbour, code, its slot) come with the call
+    auto scatter = [&](const R* u, int i, int row, int nb, int code, int fax) {
       R* const s0 = S0 + (size_t)(i * ADJ_ROWS + row) * FP;
+      if (nb < 0) {
 #pragma unroll
-      for (int f = 0; f < FP; ++f) s0[f] = u[f];
-      const int nb = FI[3 * i];
-      if (nb < 0) return;
-      const int code = FI[3 * i + 1];
-      const size_t aux = (size_t)FI[3 * i + 2];
+        for (int f = 0; f < FP; ++f) s0[f] = u[f];
+        return;
+      }
+      const size_t aux = (size_t)fax;
       const int j = code & 15, rel = ((code >> 8) & 15) - 1;
       const size_t fo = (size_t)(j * ADJ_ROWS + row) * FP;
       R* d1;
@@ -395,22 +398,41 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
         d1 = S1 + (size_t)nb * sstride + fo;
         d2 = S2 + aux * sstride + fo;
       }
+      // the slot loads first, then the S0 stores (a wait for loads issued
+      // after stores would also wait for the stores), then the updates
+      R x1[FP], x2[FP];
 #pragma unroll
-      for (int f = 0; f < FP; ++f) d1[f] += u[f];
+      for (int f = 0; f < FP; ++f) { x1[f] = d1[f]; x2[f] = R(0); }
       if (d2)
 #pragma unroll
-        for (int f = 0; f < FP; ++f) d2[f] -= u[f];
+        for (int f = 0; f < FP; ++f) x2[f] = d2[f];
+#pragma unroll
+      for (int f = 0; f < FP; ++f) s0[f] = u[f];
+#pragma unroll
+      for (int f = 0; f < FP; ++f) d1[f] = x1[f] + u[f];
+      if (d2)
+#pragma unroll
+        for (int f = 0; f < FP; ++f) d2[f] = x2[f] - u[f];
     };
+    // the face words of face i + 1 are requested before face i's trace, so
+    // their latency overlaps it
     auto faces = [&](const R* t, int row) {
       R u[FP];
-      RF::trace_f0(t, u);
-      scatter(u, 0, row);
-      RF::trace_f1(t, u);
-      scatter(u, 1, row);
-      RF::trace_f2(t, u);
-      scatter(u, 2, row);
-      RF::trace_f3(t, u);
-      scatter(u, 3, row);
+      int nb = FI[0], cd = FI[1], ax = FI[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int nb_i = nb, cd_i = cd, ax_i = ax;
+        if (i < 3) {
+          nb = FI[3 * (i + 1)];
+          cd = FI[3 * (i + 1) + 1];
+          ax = FI[3 * (i + 1) + 2];
+        }
+        if (i == 0) RF::trace_f0(t, u);
+        else if (i == 1) RF::trace_f1(t, u);
+        else if (i == 2) RF::trace_f2(t, u);
+        else RF::trace_f3(t, u);
+        scatter(u, i, row, nb_i, cd_i, ax_i);
+      }
     };
     faces(le, q);
     if (M > 0 && is_stress) {
