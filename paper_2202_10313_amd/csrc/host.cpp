@@ -165,6 +165,7 @@ int dev_alloc(edg_ctx* c, DevBuf& b, size_t bytes) {
   hipError_t e = hipMalloc(&b.p, bytes);
   if (e != hipSuccess) {
     b.p = nullptr;
+    (void)hipGetLastError();   // the failed allocation's error must not be reported by a later launch check
     return fail(c, EDG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   b.bytes = bytes;

@@ -382,6 +382,25 @@ def test_adjoint_call_errors():
         c2.set_checkpointing(1)
 
 
+def test_oversized_checkpoint_interval_is_refused():
+    """A checkpoint interval whose level-state record cannot be allocated
+    fails the advance with EDG_ENOMEM naming the bytes (the allocation is
+    refused by the runtime before any kernel runs), and a usable interval
+    works afterwards."""
+    from paper_2202_10313_amd import EdgError
+    ctx, w = _setup(2, 0, 2, True)
+    ctx.set_checkpointing(1 << 30)
+    ctx.set_initial(synth.random_state(1, ctx.K, ctx.nq, ctx.B))
+    with pytest.raises(EdgError, match="EDG_ENOMEM.*bytes"):
+        ctx.advance_to(w["sync"])
+    ctx.rewind()
+    ctx.set_checkpointing(1)
+    ctx.set_initial(synth.random_state(1, ctx.K, ctx.nq, ctx.B))
+    ctx.advance_to(w["sync"])
+    g = ctx.adjoint(dj_dq=np.ones((ctx.K, ctx.nq, ctx.B)), want_q0=True)
+    assert np.all(np.isfinite(g["q0_b"]))
+
+
 def test_device_pointer_boundary_matches_host():
     """The device-pointer forms of edg_upload_materials, edg_read_receivers
     and edg_adjoint (on_device = 1) give bit for bit what the host forms give:
