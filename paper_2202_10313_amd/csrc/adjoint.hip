@@ -944,12 +944,16 @@ void k_adjoint(KPtrs p, APtrs ad, LevelArgs a) {
 // The kernel is bound by memory latency at two waves per SIMD, so its state
 // is arranged for few dependent round trips: addresses are a scalar base plus
 // a 32-bit lane offset recomputed in the loops (no hoisted per-lane 64-bit
-// addresses to spill); the time-integral adjoints wait in De's two extra rows
-// and the memory-variable adjoint of the next derivative in Da (overwriting
-// the forward derivative once it is consumed); each face item and each mode
-// block of the coupling issue all their global loads before using any; the
-// coupling block leaves the omega-weighted sums the next step needs in the LDS
-// coupling rows; LDS reads that feed LDS stores are all issued before them.
+// addresses to spill); the per-wave scratch (forward memory-variable
+// derivatives and then their adjoints, the star-product sums of each
+// derivative's gradients, the time-integral adjoints, a copy of Qbar) is kept
+// in lane-contiguous float4 chunks, one coalesced 1 KB access per instruction;
+// the transposed surface runs one 16-lane DPP row per (element, face) pair
+// with its face parameters staged in LDS and its gradient words summed over
+// the row; the coupling block leaves the omega-weighted sums the next step
+// needs in the LDS coupling rows; LDS reads that feed LDS stores are all
+// issued before them; workgroup barriers stand only where another wave's LDS
+// data is read.
 template <class R, int O, int M>
 struct AdjLds2 {
   using RF = edg_gen::Ref<O>;
