@@ -478,7 +478,21 @@ struct Lds2 {
   static constexpr int REST = GRAD + COUP + RX;
   static constexpr int REGION = up(REST, 32, (9 * BS) % 32);   // element stride of the mode areas
   static constexpr int FACE = up(4 * 2 * LPE * FS, 32, (9 * FS) % 32);  // element stride of the face area
-  static constexpr int TOTAL = EPW * (REGION > FACE ? REGION : FACE);
+  // At O = 5 the gradient, coupling and exchange areas are three arrays with
+  // element strides of their own: the exchange keeps ES = 9 RS (mod 32) for
+  // its row-wise accesses, while the gradient and coupling strides (7 and 24
+  // mod 32) were chosen, with the slot table, for the fewest modelled
+  // conflicts of their mode-owner and slot accesses (1,112 -> 813 cycles per
+  // wave in the model).  At O = 4 that choice modelled worse: one region.
+  static constexpr bool SPLIT = O == 5;
+  static constexpr int GSTR = SPLIT ? up(GRAD, 32, 7) : REGION;
+  static constexpr int CSTR = SPLIT ? up(COUP, 32, 24) : REGION;
+  static constexpr int RSTR = SPLIT ? up(RX, 32, (9 * BS) % 32) : REGION;
+  static constexpr int GOFF = 0;
+  static constexpr int COFF = SPLIT ? EPW * GSTR : GRAD;
+  static constexpr int ROFF = SPLIT ? COFF + EPW * CSTR : GRAD + COUP;
+  static constexpr int MODES = SPLIT ? ROFF + EPW * RSTR : EPW * REGION;
+  static constexpr int TOTAL = MODES > EPW * FACE ? MODES : EPW * FACE;
 };
 
 // An opaque copy of a lane index: addresses built from it are recomputed at
@@ -493,11 +507,15 @@ __device__ __forceinline__ int fresh(int v) {
 // The assignment is the one with the fewest LDS bank conflicts (over the
 // stiffness output writes, the strain reads of the memory variables and the
 // star-product reads of a time-kernel step) found by a search over slot
-// permutations for the strides above.
+// permutations for the strides above (one table per layout of Lds2).
+template <int O>
 __device__ __forceinline__ int gslot(int row, int dir) {
-  constexpr int T[9][3] = {{1, 18, 18}, {18, 6, 18}, {18, 18, 13}, {17, 12, 18}, {18, 14, 7},
-                           {16, 18, 15}, {0, 2, 5}, {11, 10, 3}, {4, 8, 9}};
-  constexpr unsigned long long W0 = pack_rows5(T, 0), W1 = pack_rows5(T, 1), W2 = pack_rows5(T, 2);
+  constexpr int T4[9][3] = {{1, 18, 18}, {18, 6, 18}, {18, 18, 13}, {17, 12, 18}, {18, 14, 7},
+                            {16, 18, 15}, {0, 2, 5}, {11, 10, 3}, {4, 8, 9}};
+  constexpr int T5[9][3] = {{16, 18, 18}, {18, 0, 18}, {18, 18, 10}, {15, 1, 18}, {18, 12, 9},
+                            {17, 18, 11}, {7, 4, 2}, {8, 3, 14}, {6, 5, 13}};
+  constexpr unsigned long long W0 = pack_rows5(O == 5 ? T5 : T4, 0), W1 = pack_rows5(O == 5 ? T5 : T4, 1),
+                               W2 = pack_rows5(O == 5 ? T5 : T4, 2);
   const unsigned long long w = dir == 0 ? W0 : (dir == 1 ? W1 : W2);   // selects, no table in memory
   return (int)((w >> (5 * row)) & 31);
 }
@@ -542,11 +560,10 @@ void k_level2(KPtrs p, LevelArgs a) {
   const int base = w ? RF::MB1 : 0;
   const int nb = w ? NB1 : NB0;
   constexpr int BS = L::BS, FS = L::FS;
-  R* const reg = lds + ec * L::REGION;
   R* const fac = lds + ec * L::FACE;          // face area (surface phase only)
-  R* const grad = reg;
-  R* const coup = reg + L::GRAD;
-  R* const rx = reg + L::GRAD + L::COUP;
+  R* const grad = lds + L::GOFF + ec * L::GSTR;
+  R* const coup = lds + L::COFF + ec * L::CSTR;
+  R* const rx = lds + L::ROFF + ec * L::RSTR;
 
   // Global addresses are a per-workgroup (uniform, scalar) base plus a 32-bit
   // lane offset, so no 64-bit per-lane address has to stay live.
@@ -596,9 +613,9 @@ void k_level2(KPtrs p, LevelArgs a) {
   }
 
   // LDS offsets (elements of `grad`) this lane writes and reads
-  R* const gw0 = grad + gslot(q, 0) * BS;
-  R* const gw1 = grad + gslot(q, 1) * BS;
-  R* const gw2 = grad + gslot(q, 2) * BS;
+  R* const gw0 = grad + gslot<O>(q, 0) * BS;
+  R* const gw1 = grad + gslot<O>(q, 1) * BS;
+  R* const gw2 = grad + gslot<O>(q, 2) * BS;
   // Star products without divergence: every lane forms
   //   wabc (g[sa] + g[sb] + g[sc]) + wde (g[sd] + g[se]) + wc coupling
   // stress row ij: lambda delta_ij div v + mu (d_j v_i + d_i v_j) + coupling,
@@ -606,12 +623,12 @@ void k_level2(KPtrs p, LevelArgs a) {
   int sa, sb, sc, sd, se;
   R wabc, wde, wc;
   if (is_stress) {
-    sa = gslot(6, 0) * BS; sb = gslot(7, 1) * BS; sc = gslot(8, 2) * BS;
-    sd = gslot(6 + qi, qj) * BS; se = gslot(6 + qj, qi) * BS;
+    sa = gslot<O>(6, 0) * BS; sb = gslot<O>(7, 1) * BS; sc = gslot<O>(8, 2) * BS;
+    sd = gslot<O>(6 + qi, qj) * BS; se = gslot<O>(6 + qj, qi) * BS;
     wabc = lam * delta; wde = mu; wc = R(1);
   } else {
     const int i = q - 6;
-    sa = gslot(sym_index(i, 0), 0) * BS; sb = gslot(sym_index(i, 1), 1) * BS; sc = gslot(sym_index(i, 2), 2) * BS;
+    sa = gslot<O>(sym_index(i, 0), 0) * BS; sb = gslot<O>(sym_index(i, 1), 1) * BS; sc = gslot<O>(sym_index(i, 2), 2) * BS;
     sd = sa; se = sb;
     wabc = rho_inv; wde = R(0); wc = R(0);
   }
@@ -883,12 +900,12 @@ void k_level2(KPtrs p, LevelArgs a) {
         if (lb < nb) {
           R eps[6];
           if (more) {
-            eps[0] = grad[gslot(6, 0) * BS + b];
-            eps[1] = grad[gslot(7, 1) * BS + b];
-            eps[2] = grad[gslot(8, 2) * BS + b];
-            eps[3] = R(0.5) * (grad[gslot(6, 1) * BS + b] + grad[gslot(7, 0) * BS + b]);
-            eps[4] = R(0.5) * (grad[gslot(7, 2) * BS + b] + grad[gslot(8, 1) * BS + b]);
-            eps[5] = R(0.5) * (grad[gslot(6, 2) * BS + b] + grad[gslot(8, 0) * BS + b]);
+            eps[0] = grad[gslot<O>(6, 0) * BS + b];
+            eps[1] = grad[gslot<O>(7, 1) * BS + b];
+            eps[2] = grad[gslot<O>(8, 2) * BS + b];
+            eps[3] = R(0.5) * (grad[gslot<O>(6, 1) * BS + b] + grad[gslot<O>(7, 0) * BS + b]);
+            eps[4] = R(0.5) * (grad[gslot<O>(7, 2) * BS + b] + grad[gslot<O>(8, 1) * BS + b]);
+            eps[5] = R(0.5) * (grad[gslot<O>(6, 2) * BS + b] + grad[gslot<O>(8, 0) * BS + b]);
           }
           R cp[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
@@ -988,7 +1005,7 @@ void k_level2(KPtrs p, LevelArgs a) {
       for (int j = 0; j < 16; ++j) acc[j] = 0.f;
       const int kh = lane >> 5;
       const int ar = 32 * w + (lane & 31), ae = ar / LPE, aq = ar - LPE * ae;
-      const R* const arow = lds + (ae < EPW ? ae : EPW - 1) * L::REGION + L::GRAD + L::COUP + aq * BS;
+      const R* const arow = lds + L::ROFF + (ae < EPW ? ae : EPW - 1) * L::RSTR + aq * BS;
 #pragma unroll
       for (int st = 0; st < RF::MK; ++st) {
         const int k = 2 * st + kh;
@@ -1041,12 +1058,12 @@ void k_level2(KPtrs p, LevelArgs a) {
       const int lb = q + LPE * jw, b = base + lb;
       if (lb < nb) {
         R eps[6];
-        eps[0] = grad[gslot(6, 0) * BS + b];
-        eps[1] = grad[gslot(7, 1) * BS + b];
-        eps[2] = grad[gslot(8, 2) * BS + b];
-        eps[3] = R(0.5) * (grad[gslot(6, 1) * BS + b] + grad[gslot(7, 0) * BS + b]);
-        eps[4] = R(0.5) * (grad[gslot(7, 2) * BS + b] + grad[gslot(8, 1) * BS + b]);
-        eps[5] = R(0.5) * (grad[gslot(6, 2) * BS + b] + grad[gslot(8, 0) * BS + b]);
+        eps[0] = grad[gslot<O>(6, 0) * BS + b];
+        eps[1] = grad[gslot<O>(7, 1) * BS + b];
+        eps[2] = grad[gslot<O>(8, 2) * BS + b];
+        eps[3] = R(0.5) * (grad[gslot<O>(6, 1) * BS + b] + grad[gslot<O>(7, 0) * BS + b]);
+        eps[4] = R(0.5) * (grad[gslot<O>(7, 2) * BS + b] + grad[gslot<O>(8, 1) * BS + b]);
+        eps[5] = R(0.5) * (grad[gslot<O>(6, 2) * BS + b] + grad[gslot<O>(8, 0) * BS + b]);
 #pragma unroll
         for (int l = 0; l < MM; ++l)
 #pragma unroll
