@@ -1606,12 +1606,20 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     const R c_d = R(a.tc[cl][d]), h_d = R(a.th[cl][d]);
     const bool more = d + 1 < O;
     R cur[NBX];
+    // the step's scratch operands in one batch: the time-integral adjoints
+    // and the star-product sums of grad D_d (kept by the recompute) for the
+    // material pairings
+    R ab[NBX], de[NBX];
     {
       R x1[NBX], x2[NBX];
 #pragma unroll
-      for (int lb = 0; lb < NBX; ++lb) { x1[lb] = R(0); x2[lb] = R(0); }
+      for (int lb = 0; lb < NBX; ++lb) { x1[lb] = R(0); x2[lb] = R(0); ab[lb] = R(0); de[lb] = R(0); }
       ldE(SC::DT, x1);
       ldE(SC::DT + SC::CE, x2);
+      if (more) {
+        ldE(SC::DG + (2 * d) * SC::CE, ab);
+        ldE(SC::DG + (2 * d + 1) * SC::CE, de);
+      }
 #pragma unroll
       for (int lb = 0; lb < NBX; ++lb) cur[lb] = c_d * x1[lb] + h_d * x2[lb];
     }
@@ -1622,14 +1630,7 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         if (lb < nb) { cur[lb] += rd[lb]; rd[lb] = R(0); }
     }
     if (more) {
-      // material pairings with the gradients of D_d: their star-product
-      // sums were kept by the recompute
-      {
-        R ab[NBX], de[NBX];
-        ldE(SC::DG + (2 * d) * SC::CE, ab);
-        ldE(SC::DG + (2 * d + 1) * SC::CE, de);
-        star_sums(nbe, ab, de, 1.0);
-      }
+      star_sums(nbe, ab, de, 1.0);
       if (act)
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb)
