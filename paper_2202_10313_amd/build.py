@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
     _run([gen, os.path.join(CSRC, "generated", "refmats.h")] + ORDERS)
     units = [("kernels.hip", "kernels.o"), ("adjoint.hip", "adjoint.o"), ("host.cpp", "host.o"),
              ("basis.cpp", "basis.o"), ("noalloc.hip", "noalloc.o"),
-             ("materials.hip", "materials.o")]
+             ("materials.hip", "materials.o"), ("debug.hip", "debug.o")]
 
     def compile_unit(u):
         src, obj = u

@@ -125,7 +125,8 @@ __device__ __forceinline__ int step_fin_of(const LevelArgs& a, int cl) { return 
 // Linear workgroup id -> (element group, run).  Workgroups are dealt to the
 // 8 XCDs round robin; with xcd_remap the ids of one XCD cover a contiguous
 // range of the (run-major) group space, so neighbouring elements share that
-// XCD's L2.  A bijection for any grid size.
+// XCD's L2.  A bijection for any grid size; so is the optional affine shuffle
+// after it (a debug aid: it changes which groups run together and first).
 __device__ __forceinline__ void group_and_run(const LevelArgs& a, int& g, int& run) {
   const int nx = gridDim.x;
   int lin = blockIdx.x + blockIdx.y * nx;
@@ -135,6 +136,8 @@ __device__ __forceinline__ void group_and_run(const LevelArgs& a, int& g, int& r
     const int x = lin % 8, k = lin / 8;
     lin = x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
   }
+  if (a.shuf_mul)   // the host keeps lin * shuf_mul + shuf_add below 2^32
+    lin = (int)(((unsigned)lin * (unsigned)a.shuf_mul + (unsigned)a.shuf_add) % (unsigned)(nx * gridDim.y));
   g = lin % nx;
   run = a.run0 + lin / nx;
 }

@@ -19,6 +19,7 @@
 #include "edge_lts.h"
 #include "kernels.hpp"
 #include "adjoint.hpp"
+#include "debug.hpp"
 
 using namespace edg;
 
@@ -97,6 +98,8 @@ struct edg_ctx {
 
   // launch plan (all but trace_mfma give bit-identical results) and cycle graph
   edg_plan plan{0, 0, 0};
+  uint64_t shuf_seq = 0;             // launches shuffled so far (EDG_FLAG_SHUFFLE)
+  DevBuf dbg;                        // non-finite count and first index (EDG_FLAG_CHECK_FINITE)
   DevBuf dclock;                     // level at the start of the current cycle (device)
   hipGraphExec_t cycle_exec = nullptr;
   hipGraph_t cycle_graph = nullptr;
@@ -703,11 +706,95 @@ LevelArgs base_args(const edg_ctx* c) {
   return a;
 }
 
+// EDG_FLAG_SHUFFLE: a fresh affine bijection of the workgroup order of one
+// launch of `runs` runs (SplitMix64 over a per-context launch counter)
+void shuffle_args(edg_ctx* c, LevelArgs& a, int runs) {
+  a.shuf_mul = a.shuf_add = 0;
+  if (!(c->cfg.flags & EDG_FLAG_SHUFFLE)) return;
+  const long long total = (long long)((a.end + EPW - 1) / EPW) * runs;
+  if (total < 2) return;
+  auto next = [&]() {
+    uint64_t z = (c->shuf_seq += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  // 32-bit device arithmetic: (total - 1) * m + add < 2^32
+  const long long mmax = std::min<long long>(total - 1, (0xFFFFFFFFll - (total - 1)) / (total - 1));
+  long long m = 1 + (long long)(next() % (uint64_t)mmax);
+  while (std::gcd(m, total) != 1) m = m % mmax + 1;
+  a.shuf_mul = (int)m;
+  a.shuf_add = (int)(next() % (uint64_t)total);
+}
+
+// EDG_FLAG_POISON: after a level that finishes steps, NaN into the trace
+// slots whose last legal read was at that level (all runs)
+int poison_after(edg_ctx* c, const KPtrs& p, const LevelArgs& a0) {
+  const uint32_t f = c->cfg.flags;
+  if (!(f & (EDG_FLAG_POISON | EDG_FLAG_POISON_EARLY)) || a0.kind == KIND_PREDICT) return 0;
+  LevelArgs a = a0;
+  a.run0 = 0;
+  const int early = (f & EDG_FLAG_POISON_EARLY) ? 1 : 0;
+  const int rc = c->cfg.fp64 ? launch_poison_traces<double>(p, a, c->runs, c->FP, early, c->stream)
+                             : launch_poison_traces<float>(p, a, c->runs, c->FP, early, c->stream);
+  return rc ? fail(c, EDG_EHIP, std::string("poison kernel: ") + hipGetErrorString((hipError_t)rc)) : 0;
+}
+
+// EDG_FLAG_POISON: NaN into every trace slot at the start of an advance (all
+// are written before they are read from a synchronisation point on)
+int poison_all(edg_ctx* c, const KPtrs& p) {
+  if (!(c->cfg.flags & EDG_FLAG_POISON)) return 0;
+  const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
+  const void* base[3] = {p.T1, p.T2, p.T3};
+  const size_t words[3] = {c->runs * c->run_t1, c->runs * c->run_t2, c->runs * c->run_t3};
+  for (int i = 0; i < 3; ++i) {
+    const int rc = launch_poison_words(const_cast<void*>(base[i]), words[i] * rs / 4, c->stream);
+    if (rc) return fail(c, EDG_EHIP, std::string("fill kernel: ") + hipGetErrorString((hipError_t)rc));
+  }
+  return 0;
+}
+
+// EDG_FLAG_CHECK_FINITE: EDG_ENONFINITE if a DOF word of any run is NaN or
+// infinite (after an advance, with the stream synchronised)
+int check_finite(edg_ctx* c) {
+  if (!(c->cfg.flags & EDG_FLAG_CHECK_FINITE)) return 0;
+  if (!c->dbg.p) return fail(c, EDG_ESTATE, "finite check: no device counter (upload clusters first)");
+  const unsigned long long init[2] = {0ull, ~0ull};
+  HIPCHK(c, hipMemcpyAsync(c->dbg.p, init, sizeof init, hipMemcpyHostToDevice, c->stream));
+  const long long ne = (long long)(c->runs * c->run_qe), na = (long long)(c->runs * c->run_qa);
+  auto* cnt = (unsigned long long*)c->dbg.p;
+  int rc = c->cfg.fp64 ? launch_count_nonfinite<double>(c->Qe.p, ne, cnt, c->stream)
+                       : launch_count_nonfinite<float>(c->Qe.p, ne, cnt, c->stream);
+  unsigned long long ha[2] = {0, 0}, hb[2] = {0, 0};
+  if (!rc) {
+    HIPCHK(c, hipMemcpyAsync(ha, c->dbg.p, sizeof ha, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dbg.p, init, sizeof init, hipMemcpyHostToDevice, c->stream));
+    rc = c->cfg.fp64 ? launch_count_nonfinite<double>(c->Qa.p, na, cnt, c->stream)
+                     : launch_count_nonfinite<float>(c->Qa.p, na, cnt, c->stream);
+  }
+  if (rc) return fail(c, EDG_EHIP, std::string("finite check kernel: ") + hipGetErrorString((hipError_t)rc));
+  HIPCHK(c, hipMemcpyAsync(hb, c->dbg.p, sizeof hb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (ha[0] + hb[0] == 0) return 0;
+  // the first bad word -> run and caller element (Qe [run][G][B][63],
+  // Qa [run][G][JB][m][6][63]; slot 9e + q of group g is element 7g + e)
+  const bool in_e = ha[0] > 0;
+  const unsigned long long w = in_e ? ha[1] : hb[1];
+  const size_t per_run = in_e ? c->run_qe : c->run_qa;
+  const size_t run = w / per_run, rem = w % per_run, per_group = per_run / (size_t)c->G;
+  const int64_t ki = (int64_t)(rem / per_group) * EPW + (int64_t)((rem % (EPW * LPE)) / LPE);
+  const int64_t user = ki < (int64_t)c->internal_to_user.size() ? c->internal_to_user[ki] : -1;
+  return fail(c, EDG_ENONFINITE, std::to_string(ha[0] + hb[0]) + " non-finite DOF words after the advance (first: run " +
+                                     std::to_string(run) + ", element " + std::to_string(user) +
+                                     (in_e ? ", elastic rows)" : ", memory variables)"));
+}
+
 // one LTS level for all runs, in chunks of plan.run_chunk runs per launch
 int launch_runs(edg_ctx* c, const Fns& fn, const KPtrs& p, LevelArgs a) {
   const int chunk = c->plan.run_chunk > 0 ? std::min(c->plan.run_chunk, c->runs) : c->runs;
   for (int r0 = 0; r0 < c->runs; r0 += chunk) {
     a.run0 = r0;
+    shuffle_args(c, a, std::min(chunk, c->runs - r0));
     const int rc = fn.level(p, a, std::min(chunk, c->runs - r0), c->stream);
     if (rc) return fail(c, EDG_EHIP, std::string("level kernel launch: ") + hipGetErrorString((hipError_t)rc));
   }
@@ -754,7 +841,7 @@ int launch_timed(edg_ctx* c, const Fns& fn, const KPtrs& p, const LevelArgs& a, 
 edg_ctx::~edg_ctx() {
   for (DevBuf* b : {&Qe, &Qa, &P, &FI, &T1, &T2, &T3, &RecD, &s_run, &s_elem, &s_kind, &s_par, &s_mom, &s_phi,
                     &s_idet, &r_elem, &r_slot, &r_phi, &r_out, &dclock, &aLe, &aLa, &aS0, &aS1, &aS2, &aS3, &aDe, &aDa,
-                    &agacc, &arecDb, &aseis, &ahist, &afinal, &amat, &agrad, &dmat, &dflag, &d_i2u, &d_nbr})
+                    &agacc, &arecDb, &aseis, &ahist, &afinal, &amat, &agrad, &dmat, &dflag, &d_i2u, &d_nbr, &dbg})
     dev_free(*b);
   for (auto& ck : ckpts) dev_free(ck.second);
   for (auto& e : ev_pool) {
@@ -778,6 +865,9 @@ int edg_create(const edg_config* cfg, edg_ctx** out) {
   if (cfg->n_clusters < 1 || cfg->n_clusters > MAX_CLUSTERS) return EDG_EINVAL;
   if (!(cfg->cfl > 0) || cfg->lambda > 1.0 || (cfg->lambda > 0 && cfg->lambda <= 0.5)) return EDG_EINVAL;
   if (!pick(cfg->fp64, cfg->order, cfg->mechanisms).level) return EDG_EINVAL;
+  if (cfg->flags & ~(EDG_FLAG_GRAPH | EDG_FLAG_POISON | EDG_FLAG_SHUFFLE | EDG_FLAG_CHECK_FINITE |
+                     EDG_FLAG_POISON_EARLY))
+    return EDG_EINVAL;
   if (hipSetDevice(cfg->device) != hipSuccess) return EDG_EHIP;
   edg_ctx* c = new (std::nothrow) edg_ctx;
   if (!c) return EDG_ENOMEM;
@@ -1095,6 +1185,9 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   drop_graph(c);
   if ((rc = dev_alloc(c, c->dclock, sizeof(long long)))) return rc;
   HIPCHK(c, hipMemset(c->dclock.p, 0, sizeof(long long)));
+  if ((c->cfg.flags & EDG_FLAG_CHECK_FINITE) && !c->dbg.p &&
+      (rc = dev_alloc(c, c->dbg, 2 * sizeof(unsigned long long))))
+    return rc;
   c->level = 0;
   for (int l = 0; l < MAX_CLUSTERS; ++l) c->nstep[l] = 0;
   c->updates = 0;
@@ -1318,6 +1411,7 @@ int emit_cycle(edg_ctx* c, const AdvanceArgs& A, bool last, bool timed) {
     } else if ((rc = launch_runs(c, A.fn, A.p, a))) {
       return rc;
     }
+    if ((rc = poison_after(c, A.p, a))) return rc;
     if (!fin && c->n_rec > 0 && (rc = A.fn.rec(A.p, a, A.ra, c->runs, c->stream)))
       return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
   }
@@ -1386,7 +1480,9 @@ int advance_cycles(edg_ctx* c, int64_t nc, char* traces = nullptr) {
   a.kind = KIND_PREDICT;
   a.jrel = 0;
   a.end = c->cl_end[Nc - 1];
-  int rc = timed ? launch_timed(c, A.fn, A.p, a, 0) : launch_runs(c, A.fn, A.p, a);
+  int rc = poison_all(c, A.p);
+  if (rc) return rc;
+  rc = timed ? launch_timed(c, A.fn, A.p, a, 0) : launch_runs(c, A.fn, A.p, a);
   if (rc) return rc;
   if (c->n_rec > 0 && (rc = A.fn.rec(A.p, a, A.ra, c->runs, c->stream)))
     return fail(c, EDG_EHIP, std::string("receiver kernel: ") + hipGetErrorString((hipError_t)rc));
@@ -1404,6 +1500,7 @@ int advance_cycles(edg_ctx* c, int64_t nc, char* traces = nullptr) {
   }
   c->level += nc * per;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if ((rc = check_finite(c))) return rc;
   if (c->timing) {
     for (size_t i = 0; i < c->ev_used; ++i) {
       float ms = 0.f;
@@ -1483,6 +1580,7 @@ int run_recorded_levels(edg_ctx* c, const AdvanceArgs& A, const KPtrs& p, int64_
   int rc;
   LevelArgs a = base_args(c);
   a.run0 = 0;
+  if ((rc = poison_all(c, p))) return rc;
   for (int64_t j = 0; j <= (own ? J : J - 1); ++j) {
     const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
     a.jrel = (int)j;
@@ -1491,7 +1589,9 @@ int run_recorded_levels(edg_ctx* c, const AdvanceArgs& A, const KPtrs& p, int64_
     a.kind = j == 0 ? KIND_PREDICT : (j == J ? KIND_NEIGHBOR : KIND_FUSED);
     a.rec_e = j < J ? (void*)hist_rec_e(c, j) : nullptr;
     a.rec_a = (j < J && wa) ? (void*)hist_rec_a(c, j) : nullptr;
+    shuffle_args(c, a, 1);
     if ((rc = chk(A.fn.level(p, a, 1, c->stream), "level kernel"))) return rc;
+    if ((rc = poison_after(c, p, a))) return rc;
     if (own && j < J && c->n_rec > 0 && (rc = chk(A.fn.rec(p, a, A.ra, c->runs, c->stream), "receiver kernel")))
       return rc;
   }
@@ -1524,7 +1624,7 @@ int advance_recorded(edg_ctx* c, int64_t nc) {
   c->level += J;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->hist_valid = true;
-  return EDG_OK;
+  return check_finite(c);
 }
 
 // whole LTS cycles from the current time to t (EDG_ENOTSYNC unless t is a

@@ -59,6 +59,10 @@ struct LevelArgs {
   int jrel;
   int xcd_remap;     // 1: the workgroups of one XCD take a contiguous range of element groups
   int trace_mfma;    // 1: the traces of faces 0 and 1 on the matrix cores (two-wave FP32 kernel)
+  // workgroup order shuffle (debug; 0 = off): workgroup id w runs the work of
+  // id (w * shuf_mul + shuf_add) mod (workgroups of the launch), shuf_mul
+  // coprime with that count and (count - 1) * shuf_mul + shuf_add < 2^32
+  int shuf_mul, shuf_add;
   double dt[MAX_CLUSTERS];
   double tc[MAX_CLUSTERS][MAX_ORDER];  // dt^{d+1}/(d+1)!
   double th[MAX_CLUSTERS][MAX_ORDER];  // (dt/2)^{d+1}/(d+1)!

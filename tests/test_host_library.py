@@ -65,3 +65,19 @@ def test_create_rejects_bad_config():
         binding.Context(order=7)
     with pytest.raises(binding.EdgError):
         binding.Context(order=3, mechanisms=2)
+    # flag bits the header does not define
+    with pytest.raises(binding.EdgError, match="EDG_EINVAL"):
+        binding.Context(order=3, flags=32)
+    with pytest.raises(binding.EdgError, match="EDG_EINVAL"):
+        binding.Context(order=3, flags=binding.FLAG_POISON | 1 << 31)
+
+
+def test_header_flags_and_codes_match_the_binding():
+    """The debug flags and error codes the binding names are the header's."""
+    import re
+    text = open(os.path.join(ROOT, "include", "edge_lts.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (EDG_\w+) (-?\d+)u?\b", text)}
+    for name in ("GRAPH", "POISON", "SHUFFLE", "CHECK_FINITE", "POISON_EARLY"):
+        assert defs["EDG_FLAG_" + name] == getattr(binding, "FLAG_" + name)
+    for code, name in binding.ERRORS.items():
+        assert defs[name] == code
