@@ -62,5 +62,63 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer (a CPU
+# test aid): the host C++ (host.cpp, basis.cpp) compiled with g++ and both
+# sanitizers, any error fatal, linked with the HIP objects of the regular
+# build (device code is not instrumented); and the reference-matrix
+# generator built the same way.  The results are keyed by a hash of the
+# sources, so an unchanged tree is not rebuilt.  Load the library with the
+# ASan runtime preloaded (LD_PRELOAD=<sanitizer_runtime()>) and
+# EDG_LIBRARY pointing at it.
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def sanitizer_runtime() -> str:
+    return _run(["g++", "-print-file-name=libasan.so"]).stdout.strip()
+
+
+def build_sanitized_host() -> dict:
+    import hashlib
+    if not os.path.exists(LIB):
+        build()
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".cpp", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    with open(os.path.join(INCLUDE, "edge_lts.h"), "rb") as f:
+        h.update(f.read())
+    for obj in ("kernels.o", "adjoint.o", "debug.o", "materials.o", "noalloc.o"):
+        with open(os.path.join(BUILD, obj), "rb") as f:
+            h.update(f.read())
+    key = h.hexdigest()[:16]
+    lib = os.path.join(san, f"libedge_lts_san_{key}.so")
+    gen = os.path.join(san, f"gen_refmats_san_{key}")
+    if not (os.path.exists(lib) and os.path.exists(gen)):
+        cxx = ["g++", "-std=c++17", "-O1", "-g", "-fPIC"] + SANITIZE
+        inc = ["-I", CSRC, "-I", INCLUDE]
+        _run(cxx + ["-o", gen + ".tmp", os.path.join(CSRC, "gen_refmats.cpp"), os.path.join(CSRC, "basis.cpp")])
+
+        def unit(src):
+            obj = os.path.join(san, os.path.splitext(src)[0] + "_san.o")
+            extra = ["-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"] if src == "host.cpp" else []
+            _run(cxx + extra + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
+            return obj
+
+        with ThreadPoolExecutor(max_workers=2) as ex:
+            objs = list(ex.map(unit, ["host.cpp", "basis.cpp"]))
+        hip_objs = [os.path.join(BUILD, o) for o in ("kernels.o", "adjoint.o", "debug.o", "materials.o", "noalloc.o")]
+        _run(["g++", "-shared"] + SANITIZE + ["-o", lib + ".tmp"] + objs + hip_objs +
+             ["-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+        os.replace(gen + ".tmp", gen)
+        os.replace(lib + ".tmp", lib)
+        for name in os.listdir(san):   # builds of earlier sources
+            if name.startswith(("libedge_lts_san_", "gen_refmats_san_")) and key not in name:
+                os.remove(os.path.join(san, name))
+    return {"lib": lib, "gen": gen, "runtime": sanitizer_runtime()}
+
+
 if __name__ == "__main__":
     build(verbose=True)
