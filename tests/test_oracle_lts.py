@@ -209,3 +209,87 @@ def test_lts_walkthrough_trace():
     # every read happened at a level where the reader's own step ends
     for (lv, c, n) in reads:
         assert lv % 2 ** (clusters[c] - 1) == 0
+
+
+# ------------------------------------------------------- schedule checker
+
+def _piecewise_integral(preds, k, a, b, dt_k, order):
+    """Exact time integral over [a, b] of element k's predictions, split at
+    k's own step boundaries (each piece from the expansion of its step)."""
+    out, t = 0.0, a
+    while t < b - 1e-12 * dt_k:
+        t1 = min(b, (math.floor(t / dt_k + 1e-9) + 1) * dt_k)
+        out = out + _integral(preds, k, t, t1, order)
+        t = t1
+    return out
+
+
+def _schedule_errors(orc, levels):
+    """Every neighbour read of the traced run against the exact integral the
+    buffers of Sec. V-B stand for: the reader finishing its step [a, b) needs
+    the time integral of the neighbour's solution over exactly [a, b),
+    whichever buffer (B1, B2, B1 - B2 or B3) provides it.  Returns the
+    number of reads and the largest relative error."""
+    worst, n = 0.0, 0
+    for lv, c, nb, data in orc.reads:
+        lc = orc.cl[c] - 1
+        step = lv // 2 ** lc - 1
+        dt_c = orc.dt_cluster[lc]
+        a, b = step * dt_c, (step + 1) * dt_c
+        ref = _piecewise_integral(orc.preds, nb, a, b, orc.dt_cluster[orc.cl[nb] - 1], orc.O)
+        worst = max(worst, float(np.linalg.norm(data - ref) / max(np.linalg.norm(ref), 1e-300)))
+        n += 1
+    return n, worst
+
+
+def _random_schedule_oracle(n_clusters, seed, cls=None):
+    mesh = synth.layered_box(2, 2, [100.0, 200.0], 400.0, 400.0, jitter=0.15, seed=seed)
+    K = mesh["tet_verts"].shape[0]
+    mat = synth.random_materials(K, seed + 1)
+    probe = Oracle(mesh, mat, 2)
+    rng = np.random.default_rng(seed)
+    cl = lts.normalize(rng.integers(1, n_clusters + 1, K), probe.nbr)
+    orc = (cls or TracingOracle)(mesh, mat, 2, n_clusters=n_clusters, lam=1.0, clusters=cl)
+    orc.set_initial(synth.random_state(seed + 2, K, 9, orc.B))
+    return orc
+
+
+@pytest.mark.parametrize("n_clusters,seed", [(2, 1), (3, 2), (4, 3), (5, 4)])
+def test_schedule_checker_random_clusterings(n_clusters, seed):
+    """Schedule checker of the oracle: random normalised clusterings with up
+    to five clusters, two full cycles; every neighbour read is the exact
+    integral over the reader's step."""
+    orc = _random_schedule_oracle(n_clusters, seed)
+    levels = 2 * 2 ** (n_clusters - 1)
+    orc.run_traced(levels)
+    present = len(np.unique(orc.cl))
+    n, worst = _schedule_errors(orc, levels)
+    print(f"schedule N_c={n_clusters} ({present} clusters present): {n} reads, worst {worst:.2e}")
+    assert present >= min(n_clusters, 3) and n > 0
+    assert worst <= 1e-10
+
+
+class EarlyPredictOracle(TracingOracle):
+    """A planted schedule mistake: each level predicts the next step before
+    the steps that end there read the buffers."""
+
+    def run_traced(self, levels):
+        allidx = np.arange(self.K)
+        self._level = 0
+        self.predict(allidx)
+        period = 2 ** (self.cl - 1)
+        for j in range(1, levels + 1):
+            self._level = j
+            act = np.nonzero(j % period == 0)[0]
+            self.nstep[act] += 1
+            self.predict(act)
+            self.nstep[act] -= 1
+            self.update(act)
+
+
+def test_schedule_checker_flags_a_planted_mistake():
+    orc = _random_schedule_oracle(3, 2, cls=EarlyPredictOracle)
+    orc.run_traced(8)
+    n, worst = _schedule_errors(orc, 8)
+    print(f"planted early prediction: {n} reads, worst {worst:.2e}")
+    assert worst > 1e-3
