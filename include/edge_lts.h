@@ -263,19 +263,21 @@ int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cy
  * the discrete LTS scheme of Sec. III-A (Discrete Formulation) and Sec. V-B
  * (Buffers and Algorithm) as this library computes it, for gradients of
  * receiver misfits with respect to per-element rho, vp and vs.  Time steps,
- * clusters, omega and the anelastic weights Yp, Ys are held fixed.  Single
- * run contexts only (n_runs = 1). */
+ * clusters, omega and the anelastic weights Yp, Ys are held fixed.  With
+ * n_runs > 1 the misfit is the sum of the runs' misfits (the runs share the
+ * materials, as the shots of one inversion do). */
 
 /* every_cycles > 0: from now on edg_advance_to splits its cycles into
  * segments of at most every_cycles cycles and stores the state (device
- * memory, K x Nq x B words each) at the start of every segment; 0 turns it
- * off.  The final segment of each edg_advance_to call also records, at every
- * level, the state of the elements that start a step there (device memory,
- * reused by edg_adjoint; the forward kernels write it): per LTS cycle
+ * memory, n_runs x K x Nq x B words each) at the start of every segment; 0
+ * turns it off.  With one run the final segment of each edg_advance_to call
+ * also records, at every level, the state of the elements that start a step
+ * there (device memory, reused by edg_adjoint; the forward kernels write
+ * it; with several runs the reverse sweep replays that segment too): per LTS cycle
  * (element updates of the cycle) x Nq x B words, 1.9 x K x Nq x B at the
  * benchmark's three cluster sizes; an interval whose record does not fit fails
  * with EDG_ENOMEM naming the bytes it needs.  The segment runs without graph
- * replay; its launches are not counted by the timing queries.  Drops stored checkpoints.  EDG_EINVAL for n_runs > 1 or a
+ * replay; its launches are not counted by the timing queries.  Drops stored checkpoints.  EDG_EINVAL for a
  * negative interval.  The checkpoints are dropped again by edg_set_initial,
  * edg_set_dofs_subset, edg_upload_materials, edg_upload_clusters,
  * edg_set_sources and edg_rewind. */
@@ -289,18 +291,20 @@ int edg_rewind(edg_ctx* ctx);
 
 /* Reverse sweep over the advance since the first checkpoint: with the
  * derivative of a scalar misfit J with respect to the recorded seismogram
- * samples, dj_dseis [n_rec][n_samples][9] (the layout of edg_read_receivers;
- * NULL = 0), and with respect to the current DOFs, dj_dq [K][Nq][B] (caller
- * order; NULL = 0), writes dJ/d(DOFs at the first checkpoint) to g_q0
- * [K][Nq][B] and dJ/d rho, dJ/d vp, dJ/d vs [K] to g_rho, g_vp, g_vs (any may
- * be NULL).  Segments run backwards; each needs the states at the start of
+ * samples, dj_dseis [n_runs][n_rec][n_samples][9] (the layout of
+ * edg_read_receivers per run; NULL = 0), and with respect to the current
+ * DOFs, dj_dq [n_runs][K][Nq][B] (caller order; NULL = 0), writes dJ/d(DOFs
+ * at the first checkpoint) to g_q0 [n_runs][K][Nq][B] and dJ/d rho, dJ/d vp,
+ * dJ/d vs [K] (sums over the runs) to g_rho, g_vp, g_vs (any may be NULL).
+ * The runs are swept one after the other.  Segments run backwards; each needs the states at the start of
  * every level ((levels per segment) x K x Nq x B words of device memory):
- * the segment the last edg_advance_to call recorded uses them as they are,
- * every other one is first replayed forward from its checkpoint.  Then its
- * levels run backwards through the adjoint kernels.  A checkpoint interval
- * that covers the whole advance therefore needs no replay at all.  All host arrays are caller-owned and only read or written
+ * with one run, the segment the last edg_advance_to call recorded uses them
+ * as they are, every other one is first replayed forward from its
+ * checkpoint.  Then its levels run backwards through the adjoint kernels.
+ * With one run, a checkpoint interval that covers the whole advance
+ * therefore needs no replay at all.  All host arrays are caller-owned and only read or written
  * during the call; the DOFs and the time are those of before the call when it
- * returns.  EDG_ESTATE without checkpoints or for n_runs > 1.  on_device = 1:
+ * returns.  EDG_ESTATE without checkpoints.  on_device = 1:
  * all six arrays are device pointers; dj_dseis is copied and the gradients
  * are scattered to caller order on the device, while dj_dq and g_q0 (DOF
  * layout conversions done by the host) are staged through host memory. */

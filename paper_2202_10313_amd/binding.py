@@ -154,7 +154,7 @@ class Context:
         if rc != EDG_OK:
             raise EdgError(rc, "edg_create failed")
         self.h = h
-        self.order, self.m = order, mechanisms
+        self.order, self.m, self.n_runs = order, mechanisms, int(n_runs)
         self.B, self.nq = n_basis(order), 9 + 6 * mechanisms
         self.K = 0
         self.n_rec = 0
@@ -293,23 +293,29 @@ class Context:
 
     def adjoint(self, dj_dseis=None, dj_dq=None, want_q0=True):
         """Reverse sweep since the first checkpoint: returns dict(q0_b, g_rho,
-        g_vp, g_vs) for the given misfit derivatives (None = 0)."""
-        sb = None if dj_dseis is None else _f64(dj_dseis, (self.n_rec, self.n_samples, 9))
-        qb = None if dj_dq is None else _f64(dj_dq, (self.K, self.nq, self.B))
-        q0 = np.empty((self.K, self.nq, self.B)) if want_q0 else None
+        g_vp, g_vs) for the given misfit derivatives (None = 0).  With n_runs
+        > 1 the misfit is the sum over the runs: dj_dseis [runs, n_rec,
+        n_samples, 9], dj_dq and q0_b [runs, K, Nq, B]; the material
+        gradients are the sums over the runs."""
+        R = (self.n_runs,) if self.n_runs > 1 else ()
+        sb = None if dj_dseis is None else _f64(dj_dseis, R + (self.n_rec, self.n_samples, 9))
+        qb = None if dj_dq is None else _f64(dj_dq, R + (self.K, self.nq, self.B))
+        q0 = np.empty(R + (self.K, self.nq, self.B)) if want_q0 else None
         g = [np.empty(self.K) for _ in range(3)]
         self._chk(self._L.edg_adjoint(self.h, _ptr(sb), _ptr(qb), _ptr(q0), *[_ptr(a) for a in g], 0))
         return dict(q0_b=q0, g_rho=g[0], g_vp=g[1], g_vs=g[2])
 
     def adjoint_device(self, dj_dseis, dj_dq=None, want_q0=False):
         """edg_adjoint on device tensors (on_device = 1): dj_dseis [n_rec,
-        n_samples, 9] and dj_dq [K, Nq, B] CUDA float64 tensors (or None);
-        returns dict(q0_b, g_rho, g_vp, g_vs) as tensors on the same device."""
+        n_samples, 9] and dj_dq [K, Nq, B] CUDA float64 tensors (or None;
+        with a leading run axis when n_runs > 1); returns dict(q0_b, g_rho,
+        g_vp, g_vs) as tensors on the same device."""
         import torch
         dev = dj_dseis.device
-        sb = dj_dseis.to(torch.float64).contiguous()
-        qb = None if dj_dq is None else dj_dq.to(torch.float64).contiguous()
-        q0 = torch.empty((self.K, self.nq, self.B), dtype=torch.float64, device=dev) if want_q0 else None
+        R = (self.n_runs,) if self.n_runs > 1 else ()
+        sb = dj_dseis.to(torch.float64).contiguous().reshape(R + (self.n_rec, self.n_samples, 9))
+        qb = None if dj_dq is None else dj_dq.to(torch.float64).contiguous().reshape(R + (self.K, self.nq, self.B))
+        q0 = torch.empty(R + (self.K, self.nq, self.B), dtype=torch.float64, device=dev) if want_q0 else None
         g = [torch.empty(self.K, dtype=torch.float64, device=dev) for _ in range(3)]
         self._chk(self._L.edg_adjoint(self.h, _dev_ptr(sb), None if qb is None else _dev_ptr(qb),
                                       None if q0 is None else _dev_ptr(q0), *[_dev_ptr(a) for a in g], 1))

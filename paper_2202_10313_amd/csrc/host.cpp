@@ -123,6 +123,7 @@ struct edg_ctx {
   DevBuf dmat, dflag;
   DevBuf d_i2u, d_nbr;               // internal_to_user [Kp], nbr [K][4] (int64, for device-side tables)
   int64_t hist_L0 = 0, hist_J = 0;
+  int hist_run = 0;                  // the run whose level states ahist holds
   // adjoint buffers
   DevBuf aLe, aLa, aS0, aS1, aS2, aS3, aDe, aDa, agacc, arecDb, aseis, ahist, afinal, amat, agrad;
 
@@ -1513,10 +1514,11 @@ int advance_cycles(edg_ctx* c, int64_t nc, char* traces = nullptr) {
   return EDG_OK;
 }
 
-// stores the current state (run 0) as a checkpoint at the current level
+// stores the current state of every run as a checkpoint at the current
+// level: the elastic rows of all runs, then their memory variables
 int store_checkpoint(edg_ctx* c) {
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
-  const size_t we = c->run_qe, wa = c->run_qa;
+  const size_t we = c->runs * c->run_qe, wa = c->runs * c->run_qa;
   c->ckpts.emplace_back(c->level, DevBuf{});
   int rc = dev_alloc(c, c->ckpts.back().second, (we + wa) * rs);
   if (rc) {
@@ -1621,6 +1623,7 @@ int advance_recorded(edg_ctx* c, int64_t nc) {
   c->updates += nc * cycle_updates(c);
   c->hist_L0 = c->level;
   c->hist_J = J;
+  c->hist_run = 0;
   c->level += J;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->hist_valid = true;
@@ -1683,13 +1686,14 @@ int edg_advance_to(edg_ctx* c, double t) {
   if (rc0 || nc == 0) return rc0;
   if (c->ckpt_every <= 0) return advance_cycles(c, nc);
   // checkpointed: segments of at most ckpt_every cycles, each one an advance
-  // of its own that starts from a stored state; the final one records its
-  // level states, so the reverse sweep starts without a replay
+  // of its own that starts from a stored state; with one run the final one
+  // records its level states, so the reverse sweep starts without a replay
+  // (the record holds one run: with several, every segment is replayed)
   for (int64_t done = 0; done < nc;) {
     const int64_t seg = std::min<int64_t>(c->ckpt_every, nc - done);
     int rc = store_checkpoint(c);
     if (rc) return rc;
-    if ((rc = done + seg == nc ? advance_recorded(c, seg) : advance_cycles(c, seg))) return rc;
+    if ((rc = done + seg == nc && c->runs == 1 ? advance_recorded(c, seg) : advance_cycles(c, seg))) return rc;
     done += seg;
   }
   return EDG_OK;
@@ -1770,7 +1774,6 @@ int edg_read_receivers(edg_ctx* c, int32_t run, double* out, int64_t cap, int32_
 int edg_set_checkpointing(edg_ctx* c, int32_t every_cycles) {
   if (!c) return EDG_EINVAL;
   if (every_cycles < 0) return fail(c, EDG_EINVAL, "negative checkpoint interval");
-  if (every_cycles > 0 && c->runs != 1) return fail(c, EDG_EINVAL, "checkpointing needs a single run");
   (void)hipSetDevice(c->cfg.device);
   drop_checkpoints(c);
   c->ckpt_every = every_cycles;
@@ -1833,37 +1836,22 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   bool clean = c->adj_clean;
   for (int i = 0; i < 5; ++i) clean = clean && slots_before[i] == slots_now[i];
   c->adj_clean = false;
-  for (DevBuf* b : {&c->aLe, &c->aLa, &c->agacc, &c->aseis}) HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  // the gradient words sum over the runs: J is the sum of the runs' misfits
+  HIPCHK(c, hipMemsetAsync(c->agacc.p, 0, c->agacc.bytes, c->stream));
   if (!clean)
     for (DevBuf* b : {&c->aS0, &c->aS1, &c->aS2, &c->aS3, &c->arecDb})
       HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (dj_q) {
-    if (dev) {   // the DOF layout conversion runs on the host: stage through host memory
-      std::vector<double> h((size_t)c->K * c->NQ * c->B);
-      HIPCHK(c, hipMemcpy(h.data(), dj_q, h.size() * sizeof(double), hipMemcpyDeviceToHost));
-      if ((rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, h.data()))) return rc;
-    } else if ((rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, dj_q))) {
-      return rc;
-    }
-  }
-  if (dj_seis && c->n_rec > 0) {
-    const size_t bytes = (size_t)c->n_rec * c->rec_ns * LPE * sizeof(double);
-    if (dev) {
-      HIPCHK(c, hipMemcpyAsync(c->aseis.p, dj_seis, bytes, hipMemcpyDeviceToDevice, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-    } else {
-      HIPCHK(c, hipMemcpy(c->aseis.p, dj_seis, bytes, hipMemcpyHostToDevice));
-    }
-  }
   // the replays run on a state of their own, so the context's DOFs stay
-  // those of the final time
+  // those of the final time; one run at a time, so the run stride of the
+  // state is zero (the sources of run r land in the same state)
   char* rep_state = (char*)c->afinal.p;
 
-  const AdvanceArgs A = advance_args(c);
+  const AdvanceArgs A0 = advance_args(c);
   KPtrs p = kptrs(c);
   p.Qe = rep_state;
   p.Qa = rep_state + we * rs;
+  p.run_qe = p.run_qa = 0;
   APtrs ad;
   ad.Le = c->aLe.p;
   ad.La = c->aLa.p;
@@ -1881,56 +1869,103 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   auto chk = [&](int e, const char* what) {
     return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
   };
-  for (size_t si = nck; si-- > 0;) {
-    const int64_t L0 = c->ckpts[si].first;
-    const int64_t J = (si + 1 < nck ? c->ckpts[si + 1].first : L_end) - L0;
-    if (J <= 0) continue;
-    const long long clock0 = (long long)L0;
-    HIPCHK(c, hipMemcpyAsync(c->dclock.p, &clock0, sizeof clock0, hipMemcpyHostToDevice, c->stream));
+  const size_t nqb = (size_t)c->K * c->NQ * c->B, nsb = (size_t)c->n_rec * c->rec_ns * LPE;
+  size_t src_off = 0;
+  for (int run = 0; run < c->runs; ++run) {
+    // this run's sources (the device list holds the runs in order)
+    AdvanceArgs A = A0;
+    const size_t ns_run = c->src_of_run[run].size();
+    if (ns_run > 0) {
+      A.sa.n = (int)ns_run;
+      A.sa.run += src_off;
+      A.sa.elem += src_off;
+      A.sa.kind += src_off;
+      A.sa.par += 2 * src_off;
+      A.sa.moment += 6 * src_off;
+      A.sa.phi += (size_t)c->B * src_off;
+      A.sa.inv_det += src_off;
+    } else {
+      A.sa.n = 0;
+    }
+    src_off += ns_run;
+    for (DevBuf* b : {&c->aLe, &c->aLa, &c->aseis}) HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    LevelArgs a = base_args(c);
-    a.run0 = 0;
-    if (!(c->hist_valid && c->hist_L0 == L0 && c->hist_J == J)) {
-      // restore the segment's start and replay it forward, keeping the state
-      // at the start of every level's predictions
-      c->hist_valid = false;
-      const char* ck = (const char*)c->ckpts[si].second.p;
-      HIPCHK(c, hipMemcpyAsync(rep_state, ck, (we + wa) * rs, hipMemcpyDeviceToDevice, c->stream));
-      if ((rc = run_recorded_levels(c, A, p, J, false))) return rc;
+    if (dj_q) {
+      const double* q = dj_q + run * nqb;
+      if (dev) {   // the DOF layout conversion runs on the host: stage through host memory
+        std::vector<double> h(nqb);
+        HIPCHK(c, hipMemcpy(h.data(), q, nqb * sizeof(double), hipMemcpyDeviceToHost));
+        if ((rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, h.data()))) return rc;
+      } else if ((rc = set_dofs_to<R>(c, c->aLe.p, c->aLa.p, q))) {
+        return rc;
+      }
+    }
+    if (dj_seis && c->n_rec > 0) {
+      const double* sb = dj_seis + run * nsb;
+      if (dev) {
+        HIPCHK(c, hipMemcpyAsync(c->aseis.p, sb, nsb * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+      } else {
+        HIPCHK(c, hipMemcpy(c->aseis.p, sb, nsb * sizeof(double), hipMemcpyHostToDevice));
+      }
+    }
+    for (size_t si = nck; si-- > 0;) {
+      const int64_t L0 = c->ckpts[si].first;
+      const int64_t J = (si + 1 < nck ? c->ckpts[si + 1].first : L_end) - L0;
+      if (J <= 0) continue;
+      const long long clock0 = (long long)L0;
+      HIPCHK(c, hipMemcpyAsync(c->dclock.p, &clock0, sizeof clock0, hipMemcpyHostToDevice, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
-      c->hist_L0 = L0;
-      c->hist_J = J;
-      c->hist_valid = true;
-    }
-    // the levels backwards: transposed predictions, then transposed updates
-    for (int64_t j = J; j >= 0; --j) {
-      const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
-      a.jrel = (int)j;
-      a.end = c->cl_end[lmax];
-      if (j < J) {
-        if (c->n_rec > 0 && dj_seis &&
-            (rc = chk(launch_receivers_adj<R, O, M>(p, ad, a, A.ra, seis_b, c->stream), "receiver adjoint kernel")))
-          return rc;
-        ad.Se = hist_e(j);
-        ad.Sa = hist_a(j);
-        a.kind = KIND_ADJ_PREDICT;
-        if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+      LevelArgs a = base_args(c);
+      a.run0 = 0;
+      if (!(c->hist_valid && c->hist_L0 == L0 && c->hist_J == J && c->hist_run == run)) {
+        // restore this run's state at the segment's start (checkpoints hold
+        // the elastic rows of all runs, then their memory variables) and
+        // replay the segment forward, keeping the state at the start of
+        // every level's predictions
+        c->hist_valid = false;
+        const char* ck = (const char*)c->ckpts[si].second.p;
+        HIPCHK(c, hipMemcpyAsync(rep_state, ck + run * we * rs, we * rs, hipMemcpyDeviceToDevice, c->stream));
+        if (wa)
+          HIPCHK(c, hipMemcpyAsync(rep_state + we * rs, ck + (c->runs * we + run * wa) * rs, wa * rs,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        if ((rc = run_recorded_levels(c, A, p, J, false))) return rc;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->hist_L0 = L0;
+        c->hist_J = J;
+        c->hist_run = run;
+        c->hist_valid = true;
       }
-      if (j > 0) {
-        a.kind = KIND_ADJ_UPDATE;
-        if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+      // the levels backwards: transposed predictions, then transposed updates
+      for (int64_t j = J; j >= 0; --j) {
+        const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
+        a.jrel = (int)j;
+        a.end = c->cl_end[lmax];
+        if (j < J) {
+          if (c->n_rec > 0 && dj_seis &&
+              (rc = chk(launch_receivers_adj<R, O, M>(p, ad, a, A.ra, seis_b, c->stream), "receiver adjoint kernel")))
+            return rc;
+          ad.Se = hist_e(j);
+          ad.Sa = hist_a(j);
+          a.kind = KIND_ADJ_PREDICT;
+          if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+        }
+        if (j > 0) {
+          a.kind = KIND_ADJ_UPDATE;
+          if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+        }
       }
+      HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-  }
-  // outputs
-  if (g_q0) {
-    if (dev) {
-      std::vector<double> h((size_t)c->K * c->NQ * c->B);
-      if ((rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, h.data()))) return rc;
-      HIPCHK(c, hipMemcpy(g_q0, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
-    } else if ((rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, g_q0))) {
-      return rc;
+    if (g_q0) {
+      double* out = g_q0 + run * nqb;
+      if (dev) {
+        std::vector<double> h(nqb);
+        if ((rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, h.data()))) return rc;
+        HIPCHK(c, hipMemcpy(out, h.data(), nqb * sizeof(double), hipMemcpyHostToDevice));
+      } else if ((rc = get_dofs_from<R>(c, c->aLe.p, c->aLa.p, out))) {
+        return rc;
+      }
     }
   }
   if (g_rho || g_vp || g_vs) {
@@ -2003,7 +2038,6 @@ int edg_adjoint(edg_ctx* c, const double* dj_dseis, const double* dj_dq, double*
   if (!c) return EDG_EINVAL;
   if (on_device != 0 && on_device != 1) return fail(c, EDG_EINVAL, "on_device must be 0 or 1");
   if (!c->have_clusters) return fail(c, EDG_ESTATE, "upload clusters first");
-  if (c->runs != 1) return fail(c, EDG_ESTATE, "the adjoint needs a single run");
   if (c->ckpt_every <= 0 || c->ckpts.empty())
     return fail(c, EDG_ESTATE, "no checkpoints: enable checkpointing before the forward advance");
   if (c->ckpts.back().first > c->level) return fail(c, EDG_ESTATE, "checkpoints are ahead of the current time");

@@ -359,9 +359,9 @@ def test_adjoint_5k_tets_order4(mech):
 
 
 def test_adjoint_call_errors():
-    """No checkpoints, dropped checkpoints and batched contexts are refused
-    with EDG_ESTATE / EDG_EINVAL instead of computing anything."""
-    from paper_2202_10313_amd import Context, EdgError
+    """No checkpoints, dropped checkpoints and a negative interval are
+    refused with EDG_ESTATE / EDG_EINVAL instead of computing anything."""
+    from paper_2202_10313_amd import EdgError
     ctx, w = _setup(2, 0, 2, True)
     with pytest.raises(EdgError, match="EDG_ESTATE"):
         ctx.adjoint()
@@ -373,13 +373,6 @@ def test_adjoint_call_errors():
         ctx.adjoint()
     with pytest.raises(EdgError, match="EDG_EINVAL"):
         ctx.set_checkpointing(-1)
-    mesh, mat = _mesh()
-    c2 = Context(2, mechanisms=0, n_clusters=1, fp64=True, n_runs=2)
-    c2.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
-    c2.upload_materials(mat["rho"], mat["vp"], mat["vs"])
-    c2.upload_clusters(None)
-    with pytest.raises(EdgError, match="EDG_EINVAL"):
-        c2.set_checkpointing(1)
 
 
 def test_oversized_checkpoint_interval_is_refused():
@@ -472,3 +465,65 @@ def test_autograd_stale_backward_raises():
         J1.backward()
     J2.backward()
     assert all(torch.isfinite(p.grad).all() and p.grad.abs().sum() > 0 for p in ps2)
+
+
+def _runs_setup(order, fp64, n_runs, srcs):
+    """A context of n_runs runs on the adjoint tests' mesh, each run with its
+    own sources (srcs[r]: list of (xyz, moment) or empty)."""
+    from paper_2202_10313_amd import Context
+    mesh, mat = _mesh()
+    attn = synth.attenuation_inputs(mat, 3, 0.1, 10.0)
+    ctx = Context(order, mechanisms=3, n_clusters=2, fp64=fp64, cfl=0.5, lam=None, n_runs=n_runs)
+    ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+    ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+    ctx.upload_clusters(None)
+    for r, s in enumerate(srcs):
+        if s:
+            xyz = np.array([p[0] for p in s])
+            mom = np.array([p[1] for p in s])
+            ctx.set_sources(xyz, mom, 0, np.tile(SRC["stf_params"], (len(s), 1)), run=r)
+    ctx.set_receivers(REC["xyz"], REC["dt_sample"], REC["n_samples"])
+    return ctx
+
+
+@pytest.mark.parametrize("order,fp64,every", [(3, True, 1), (5, False, 2)])
+def test_multi_run_adjoint_equals_single_runs(order, fp64, every):
+    """n_runs = 3 (one source, none, two sources): the adjoint DOFs of each
+    run equal the single-run sweep of that run, and the material gradients
+    equal the sum of the single-run gradients."""
+    srcs = [[(SRC["xyz"][0], SRC["moment"][0])], [],
+            [(np.array([120.0, 280.0, -60.0]), SRC["moment"][0] * 0.5),
+             (np.array([300.0, 120.0, -250.0]), SRC["moment"][0][::-1].copy())]]
+    print(f"[adjoint] 3 runs O={order} {'FP64' if fp64 else 'FP32'} every={every}", flush=True)
+    rng = np.random.default_rng(order)
+    ctx = _runs_setup(order, fp64, 3, srcs)
+    sync = ctx.get_clusters()["sync_dt"]
+    xs = [synth.random_state(70 + r, ctx.K, ctx.nq, ctx.B) for r in range(3)]
+    y = rng.standard_normal((3, ctx.K, ctx.nq, ctx.B)) * np.where(np.arange(ctx.nq) < 6, 1e-6, 1.0)[None, None, :, None]
+    sb = rng.standard_normal((3, len(REC["xyz"]), REC["n_samples"], 9))
+    ctx.set_checkpointing(every)
+    for r in range(3):
+        ctx.set_initial(xs[r], run=r)
+    ctx.advance_to(4 * sync)
+    qT = [ctx.read_dofs(run=r) for r in range(3)]
+    res = ctx.adjoint(dj_dseis=sb, dj_dq=y)
+    assert res["q0_b"].shape == (3, ctx.K, ctx.nq, ctx.B)
+    assert all(np.array_equal(qT[r], ctx.read_dofs(run=r)) for r in range(3))
+    g_sum = {k: 0.0 for k in ("g_rho", "g_vp", "g_vs")}
+    tol_q, tol_g = (1e-12, 1e-12) if fp64 else (2e-6, 2e-5)
+    for r in range(3):
+        one = _runs_setup(order, fp64, 1, [srcs[r]])
+        one.set_checkpointing(every)
+        one.set_initial(xs[r])
+        one.advance_to(4 * sync)
+        assert np.array_equal(one.read_dofs(), qT[r])
+        ref = one.adjoint(dj_dseis=sb[r], dj_dq=y[r])
+        e = parity(res["q0_b"][r], ref["q0_b"])
+        print(f"[adjoint] run {r}: adjoint DOFs vs single run {e:.2e}", flush=True)
+        assert e <= tol_q
+        for k in g_sum:
+            g_sum[k] = g_sum[k] + ref[k]
+        one.close()
+    eg = max(np.linalg.norm(res[k] - g_sum[k]) / np.linalg.norm(g_sum[k]) for k in g_sum)
+    print(f"[adjoint] gradient vs sum of single runs {eg:.2e}", flush=True)
+    assert eg <= tol_g
