@@ -290,7 +290,8 @@ def main():
         every `every` cycles; the final segment records its level states) plus
         the reverse sweep (replay of every other segment from its checkpoint,
         adjoint kernels backwards).  One untimed cycle first."""
-        ctx = Context(order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream)
+        ctx = Context(order, mechanisms=3, n_clusters=3, fp64=False, cfl=0.5, lam=None, stream=stream.cuda_stream,
+                      flags=FLAG_GRAPH if args.graph else 0)
         ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
         ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
         ctx.upload_clusters(None)

@@ -83,7 +83,9 @@ typedef struct {
 
 #define EDG_FLAG_GRAPH 1u  /* replay every full LTS cycle but the last of an edg_advance_to call as one
                               captured HIP graph (kernel nodes only; recaptured after a change of
-                              sources, receivers, clusters or launch plan) */
+                              sources, receivers, clusters or launch plan); edg_adjoint replays the
+                              backward levels of its segments as graphs captured once per segment
+                              length in that call */
 /* Debug aids for the buffer schedule of Sec. V-B (Buffers and Algorithm); none changes a result that
  * is computed from legally read data, so with them on, a correct run gives bit-identical DOFs and
  * seismograms (they cost extra launches, so they are for tests, not production). */

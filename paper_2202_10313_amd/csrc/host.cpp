@@ -1869,6 +1869,46 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
   auto chk = [&](int e, const char* what) {
     return e ? fail(c, EDG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e)) : 0;
   };
+  // the levels of a segment backwards: transposed predictions, then
+  // transposed updates (kernel launches only)
+  auto backward = [&](LevelArgs a, int64_t J) {
+    int e;
+    for (int64_t j = J; j >= 0; --j) {
+      const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
+      a.jrel = (int)j;
+      a.end = c->cl_end[lmax];
+      if (j < J) {
+        if (c->n_rec > 0 && dj_seis &&
+            (e = chk(launch_receivers_adj<R, O, M>(p, ad, a, A0.ra, seis_b, c->stream), "receiver adjoint kernel")))
+          return e;
+        ad.Se = hist_e(j);
+        ad.Sa = hist_a(j);
+        a.kind = KIND_ADJ_PREDICT;
+        if ((e = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return e;
+      }
+      if (j > 0) {
+        a.kind = KIND_ADJ_UPDATE;
+        if ((e = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return e;
+      }
+    }
+    return 0;
+  };
+  const bool graph = (c->cfg.flags & EDG_FLAG_GRAPH) != 0;
+  struct SegGraph {
+    int64_t J;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<SegGraph> graphs;
+  struct GraphsGuard {   // the graphs live for this sweep only
+    std::vector<SegGraph>& v;
+    ~GraphsGuard() {
+      for (auto& q : v) {
+        if (q.x) (void)hipGraphExecDestroy(q.x);
+        if (q.g) (void)hipGraphDestroy(q.g);
+      }
+    }
+  } graphs_guard{graphs};
   const size_t nqb = (size_t)c->K * c->NQ * c->B, nsb = (size_t)c->n_rec * c->rec_ns * LPE;
   size_t src_off = 0;
   for (int run = 0; run < c->runs; ++run) {
@@ -1936,24 +1976,24 @@ int adjoint_sweep(edg_ctx* c, const double* dj_seis, const double* dj_q, double*
         c->hist_run = run;
         c->hist_valid = true;
       }
-      // the levels backwards: transposed predictions, then transposed updates
-      for (int64_t j = J; j >= 0; --j) {
-        const int lmax = (j == 0 || j == J) ? Nc - 1 : level_lmax(c, j);
-        a.jrel = (int)j;
-        a.end = c->cl_end[lmax];
-        if (j < J) {
-          if (c->n_rec > 0 && dj_seis &&
-              (rc = chk(launch_receivers_adj<R, O, M>(p, ad, a, A.ra, seis_b, c->stream), "receiver adjoint kernel")))
-            return rc;
-          ad.Se = hist_e(j);
-          ad.Sa = hist_a(j);
-          a.kind = KIND_ADJ_PREDICT;
-          if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
+      if (graph) {
+        // the backward levels of a segment depend on its length only (the
+        // record is addressed from the segment start, the clock is device
+        // memory): captured once per length, replayed for every segment and run
+        size_t gi = 0;
+        while (gi < graphs.size() && graphs[gi].J != J) ++gi;
+        if (gi == graphs.size()) {
+          graphs.push_back({J, nullptr, nullptr});
+          HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+          rc = backward(a, J);
+          const hipError_t e = hipStreamEndCapture(c->stream, &graphs[gi].g);
+          if (rc) return rc;
+          if (e != hipSuccess) return fail(c, EDG_EHIP, std::string("adjoint graph capture: ") + hipGetErrorString(e));
+          HIPCHK(c, hipGraphInstantiate(&graphs[gi].x, graphs[gi].g, nullptr, nullptr, 0));
         }
-        if (j > 0) {
-          a.kind = KIND_ADJ_UPDATE;
-          if ((rc = chk(launch_adjoint<R, O, M>(p, ad, a, c->stream), "adjoint kernel"))) return rc;
-        }
+        HIPCHK(c, hipGraphLaunch(graphs[gi].x, c->stream));
+      } else if ((rc = backward(a, J))) {
+        return rc;
       }
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }

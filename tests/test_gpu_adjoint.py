@@ -527,3 +527,40 @@ def test_multi_run_adjoint_equals_single_runs(order, fp64, every):
     eg = max(np.linalg.norm(res[k] - g_sum[k]) / np.linalg.norm(g_sum[k]) for k in g_sum)
     print(f"[adjoint] gradient vs sum of single runs {eg:.2e}", flush=True)
     assert eg <= tol_g
+
+
+@pytest.mark.parametrize("order,fp64", [(3, True), (5, False)])
+def test_graph_captured_reverse_sweep(order, fp64):
+    """EDG_FLAG_GRAPH: the backward levels of each segment are captured once
+    per segment length and replayed (segments of 4, 4 and 2 levels, two
+    runs, two sweeps in a row); the results equal the eager sweep."""
+    from paper_2202_10313_amd import FLAG_GRAPH
+    print(f"[adjoint] graph-captured sweep O={order} {'FP64' if fp64 else 'FP32'}", flush=True)
+    srcs = [[(SRC["xyz"][0], SRC["moment"][0])], [(np.array([120.0, 280.0, -60.0]), SRC["moment"][0] * 0.5)]]
+    rng = np.random.default_rng(3)
+    out = []
+    for flags in (0, FLAG_GRAPH):
+        from paper_2202_10313_amd import Context
+        mesh, mat = _mesh()
+        attn = synth.attenuation_inputs(mat, 3, 0.1, 10.0)
+        ctx = Context(order, mechanisms=3, n_clusters=2, fp64=fp64, cfl=0.5, lam=None, n_runs=2, flags=flags)
+        ctx.upload_mesh(mesh["tet_verts"], mesh["tet_xyz"], mesh["face_bc"])
+        ctx.upload_materials(mat["rho"], mat["vp"], mat["vs"], attn["omega"], attn["yp"], attn["ys"])
+        ctx.upload_clusters(None)
+        for r, s in enumerate(srcs):
+            ctx.set_sources(np.array([s[0][0]]), np.array([s[0][1]]), 0, SRC["stf_params"], run=r)
+            ctx.set_initial(synth.random_state(90 + r, ctx.K, ctx.nq, ctx.B), run=r)
+        ctx.set_receivers(REC["xyz"], REC["dt_sample"], REC["n_samples"])
+        ctx.set_checkpointing(2)
+        ctx.advance_to(5 * ctx.get_clusters()["sync_dt"])
+        if not out:
+            y = rng.standard_normal((2, ctx.K, ctx.nq, ctx.B)) * 1e-3
+            sb = rng.standard_normal((2, len(REC["xyz"]), REC["n_samples"], 9))
+        out.append([ctx.adjoint(dj_dseis=sb, dj_dq=y) for _ in range(2)])
+        ctx.close()
+    tol = 1e-13 if fp64 else 1e-6
+    for eager, graph in zip(out[0], out[1]):
+        for key in ("q0_b", "g_rho", "g_vp", "g_vs"):
+            e = np.linalg.norm(eager[key] - graph[key]) / np.linalg.norm(eager[key])
+            print(f"[adjoint] graph vs eager {key}: {e:.2e}", flush=True)
+            assert e <= tol, key
