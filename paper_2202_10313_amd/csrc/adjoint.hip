@@ -984,12 +984,18 @@ struct AdjScratch2 {
   static constexpr int JW = (NBX + LPE - 1) / LPE;
   static constexpr int MM = M > 0 ? M : 1;
   static constexpr int CE = (NBX + 3) / 4, CA = (6 * MM + 3) / 4;
-  static constexpr int DA = 0;                       // [O][JW] forward D_d^a, then its adjoint
-  static constexpr int DG = DA + O * JW * CA;        // [O - 1][2] star-product sums of grad D_d
+  static constexpr int C6 = M > 0 ? 2 : 0;          // chunks of six words (one strain-like tensor)
+  // memory variables: the adjoint of D_d^a is a closed-form sum over the
+  // coupling adjoints of the steps >= d, so the scratch keeps those (six
+  // words per mode and step) rather than D_d^a and its adjoint per mechanism
+  static constexpr int EP = 0;                       // [O - 1][JW] strain rates of D_d (forward)
+  static constexpr int HS = EP + (O - 1) * JW * C6;  // [O][JW] coupling adjoints cq_d
+  static constexpr int LM = HS + O * JW * C6;        // [O][JW] the steps' Qbar^a terms (Lambda_d)
+  static constexpr int DG = LM + O * JW * C6;        // [O - 1][2] star-product sums of grad D_d
   static constexpr int DT = DG + (O - 1) * 2 * CE;   // [2] time-integral adjoints (Δt, Δt/2)
   static constexpr int LE = DT + 2 * CE;             // Qbar's elastic rows (own modes)
-  static constexpr int LA = LE + CE;                 // [JW] Qbar's memory variables
-  static constexpr int CHUNKS = LA + JW * CA;
+  static constexpr int LA = LE + CE;                 // [JW] Qbar's memory variables (M > 0)
+  static constexpr int CHUNKS = LA + (M > 0 ? JW * CA : 0);
   static constexpr int WAVE_FLOATS = CHUNKS * 64 * 4;
 };
 template <int N>
@@ -1079,6 +1085,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   auto ldE = [&](int chunk, R* v) { ld_chunks<NBX>(SW + chunk * 256, l4, v); };
   auto stA = [&](int chunk, const R* v) { st_chunks<6 * MM>(SW + chunk * 256, l4, v); };
   auto ldA = [&](int chunk, R* v) { ld_chunks<6 * MM>(SW + chunk * 256, l4, v); };
+  auto st6 = [&](int chunk, const R* v) { st_chunks<6>(SW + chunk * 256, l4, v); };
+  auto ld6 = [&](int chunk, R* v) { ld_chunks<6>(SW + chunk * 256, l4, v); };
   const size_t sstride = (size_t)4 * ADJ_ROWS * FP;
 
   const bool is_stress = q < 6;
@@ -1199,9 +1207,6 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
         for (int lb = 0; lb < NBX; ++lb) dv[lb] = lb < nb ? rx[q * BS + base + lb] : R(0);
 #pragma unroll
         for (int lb = 0; lb < NBX; ++lb) { te[lb] += c_d * dv[lb]; t2[lb] += h_d * dv[lb]; }
-        if (M > 0)
-#pragma unroll
-          for (int jw = 0; jw < JW; ++jw) stA(SC::DA + (d * JW + jw) * SC::CA, &dm[jw][0][0]);
       }
       if (!more) break;
       {
@@ -1224,6 +1229,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
             eps[3] = R(0.5) * (grad[aslot(6, 1) * BS + b] + grad[aslot(7, 0) * BS + b]);
             eps[4] = R(0.5) * (grad[aslot(7, 2) * BS + b] + grad[aslot(8, 1) * BS + b]);
             eps[5] = R(0.5) * (grad[aslot(6, 2) * BS + b] + grad[aslot(8, 0) * BS + b]);
+            // (the gradient words' pass at the end rebuilds D_d^a from these)
+            st6(SC::EP + (d * JW + jw) * SC::C6, eps);
             R cp[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
             for (int l = 0; l < MM; ++l) {
@@ -1516,7 +1523,29 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       for (int l = 0; l < MM; ++l)
 #pragma unroll
         for (int c = 0; c < 6; ++c) lv[l * 6 + c] = lb < nb ? la_at(jb, l, c) : R(0);
-      stA(SC::LA + jw * SC::CA, lv);               // for the reverse loop's coupling blocks
+      stA(SC::LA + jw * SC::CA, lv);               // for the final Qbar^a update
+      // Lambda_d = sum_l omega_l^2 C_l(d) Qbar^a_l, C_l(d) = sum_{k >= d}
+      // (-omega_l)^(k - d) c_k: the Qbar^a part of the omega-weighted
+      // memory-variable adjoints of step d (see the reverse loop)
+      {
+        R Cl[MM];
+#pragma unroll
+        for (int l = 0; l < MM; ++l) Cl[l] = R(0);
+#pragma unroll
+        for (int d = O - 1; d >= 0; --d) {
+          const R c_d = R(a.tc[cl][d]);
+          R lm[6];
+#pragma unroll
+          for (int l = 0; l < MM; ++l) Cl[l] = c_d - om[l] * Cl[l];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            lm[c] = R(0);
+#pragma unroll
+            for (int l = 0; l < MM; ++l) lm[c] += om[l] * om[l] * Cl[l] * lv[l * 6 + c];
+          }
+          if (lb < nb) st6(SC::LM + (d * JW + jw) * SC::C6, lm);
+        }
+      }
       if (lb < nb && act)
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -1592,10 +1621,9 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   // modes of the exchange rows, which the transposed product does not read)
 
   // ---------------------------------------------- time kernel backwards
-  // nbe: adjoint of the next elastic derivative (registers); the adjoint of
-  // the next memory-variable derivative is carried in Da: iteration d reads
-  // the forward D_d there, then overwrites it with its adjoint, which
-  // iteration d - 1 reads
+  // nbe: adjoint of the next elastic derivative (registers); the
+  // memory-variable adjoints are not carried: each step forms their
+  // omega-weighted sum from the coupling adjoints of the steps before it
   R nbe[NBX];
 #pragma unroll
   for (int lb = 0; lb < NBX; ++lb) nbe[lb] = R(0);
@@ -1648,8 +1676,8 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
     }
     if (M > 0) {
       // the coupling E: cq_d enters the volume term c_d cq_d and the next
-      // derivative.  The global operands of a mode block (forward D_d, the
-      // carried adjoint, Qbar's memory variables) are loaded in one batch.
+      // derivative.  The scratch operands of a mode block (Lambda_d and the
+      // coupling adjoints of the later steps) are loaded in one batch.
       if (is_stress && act) {
         R lev[NBX];
         ldE(SC::LE, lev);
@@ -1659,45 +1687,52 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
       }
       // the stress rows of a mode are read by its owner, in the same wave
       wave_lds_sync();
-      // the anelastic-weight words of both mode blocks, added once per step
-      double gab[2 * MM];
+      // The adjoint of D_d^a in closed form: with s_l(k) = b_l cq_k + a_l
+      // tr(cq_k) I (cq_k: the coupling adjoint of step k),
+      //   abar_{l,d} = -omega_l C_l(d) Qbar^a_l - sum_{k >= d} (-omega_l)^(k-d) s_l(k),
+      // so its omega-weighted sum over l, which the next (lower) derivative
+      // needs, is -Lambda_d - sum_{k >= d} (beta_{k-d} cq_k + alpha_{k-d}
+      // tr(cq_k) I) with beta_j = sum_l omega_l (-omega_l)^j b_l (alpha_j with
+      // a_l).  The scratch keeps cq_k (six words) instead of the carried
+      // adjoints of every mechanism.
+      R bet[O], alp[O];
 #pragma unroll
-      for (int k = 0; k < 2 * MM; ++k) gab[k] = 0.0;
+      for (int j = 0; j < O; ++j) { bet[j] = R(0); alp[j] = R(0); }
+#pragma unroll
+      for (int l = 0; l < MM; ++l) {
+        R pw = om[l];
+#pragma unroll
+        for (int j = 0; j < O; ++j) {
+          bet[j] += pw * bl[l];
+          alp[j] += pw * al[l];
+          pw *= -om[l];
+        }
+      }
 #pragma unroll
       for (int jw = 0; jw < JW; ++jw) {
-        const int lb = q + LPE * jw, b = base + lb, jb = jb0 + jw;
+        const int lb = q + LPE * jw, b = base + lb;
         if (lb < nb) {
-          R dmd[MM][6], nxt[MM][6], lav[MM][6];
-          ldA(SC::DA + (d * JW + jw) * SC::CA, &dmd[0][0]);
-#pragma unroll
-          for (int l = 0; l < MM; ++l)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) nxt[l][c] = R(0);
-          if (more) ldA(SC::DA + ((d + 1) * JW + jw) * SC::CA, &nxt[0][0]);
-          ldA(SC::LA + jw * SC::CA, &lav[0][0]);
-          R cqb[6];
+          R cqb[6], lm[6], hk[O - 1][6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) cqb[c] = rx[c * BS + b];
-          const R cqt = cqb[0] + cqb[1] + cqb[2];
-          R ws[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-          R vv[MM][6];
+          ld6(SC::LM + (d * JW + jw) * SC::C6, lm);
 #pragma unroll
-          for (int l = 0; l < MM; ++l) {
-            const R tr = dmd[l][0] + dmd[l][1] + dmd[l][2];
-            double ga = -(double)(cqt * tr), gbb = 0.0;
+          for (int kk = 0; kk < O - 1; ++kk) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) gbb -= (double)(cqb[c] * dmd[l][c]);
-            gab[2 * l] += ga;
-            gab[2 * l + 1] += gbb;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-              const R v = -om[l] * (c_d * lav[l][c] + nxt[l][c]) - bl[l] * cqb[c] - (c < 3 ? al[l] * cqt : R(0));
-              vv[l][c] = v;
-              ws[c] += om[l] * v;
-            }
+            for (int c = 0; c < 6; ++c) hk[kk][c] = R(0);
+            if (d + 1 + kk < O) ld6(SC::HS + ((d + 1 + kk) * JW + jw) * SC::C6, hk[kk]);
           }
-          // the adjoint of D_d^a replaces D_d^a (the next step reads it)
-          stA(SC::DA + (d * JW + jw) * SC::CA, &vv[0][0]);
+          st6(SC::HS + (d * JW + jw) * SC::C6, cqb);
+          R ws[6];
+          const R cqt = cqb[0] + cqb[1] + cqb[2];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) ws[c] = -lm[c] - bet[0] * cqb[c] - (c < 3 ? alp[0] * cqt : R(0));
+#pragma unroll
+          for (int kk = 0; kk < O - 1; ++kk) {
+            const R ht = hk[kk][0] + hk[kk][1] + hk[kk][2];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) ws[c] -= bet[kk + 1] * hk[kk][c] + (c < 3 ? alp[kk + 1] * ht : R(0));
+          }
           // the coupling term of the next (lower) derivative's adjoint: coup
           // is not touched again before the next step reads it
           if (act)
@@ -1705,9 +1740,6 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
             for (int c = 0; c < 6; ++c) coup[c * BS + b] = ws[c];
         }
       }
-      if (valid)
-#pragma unroll
-        for (int k = 0; k < 2 * MM; ++k) gadd(gs, 5 + k, gab[k]);
       wave_lds_sync();
     }
 #pragma unroll
@@ -1717,29 +1749,89 @@ void k_adjoint2(KPtrs p, APtrs ad, LevelArgs a) {
   // read-modify-write per word would wait one memory latency per word: the
   // compiler must assume each store may alias the next load)
   if (valid) {
-    R xe[NBX], xa[JW][MM][6], xd[JW][MM][6];
+    R xe[NBX];
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb) xe[lb] = R(0);
     ldE(SC::LE, xe);                               // Qbar as staged (unchanged until here)
-    if (M > 0)
-#pragma unroll
-      for (int jw = 0; jw < JW; ++jw) {
-        ldA(SC::LA + jw * SC::CA, &xa[jw][0][0]);
-        ldA(SC::DA + jw * SC::CA, &xd[jw][0][0]);
-      }
 #pragma unroll
     for (int lb = 0; lb < NBX; ++lb)
       if (lb < nb) at(Le, (base + lb) * NSLOT + slot) = xe[lb] + nbe[lb];
-    if (M > 0)
+  }
+  double gab[2 * MM];
 #pragma unroll
-      for (int jw = 0; jw < JW; ++jw) {
-        const int lb = q + LPE * jw, jb = jb0 + jw;
-        if (lb < nb)
+  for (int k = 0; k < 2 * MM; ++k) gab[k] = 0.0;
+  if (M > 0 && valid) {
+    // per owned mode block: Qbar^a_l += abar_{l,0} = -omega_l C_l(0) Qbar^a_l
+    // - sum_k (-omega_l)^k s_l(k); and the anelastic-weight words
+    // -sum_d cq_d . D_d^a_l (tensor and trace parts), with D_d^a rebuilt
+    // from the state's memory variables and the stored strain rates by the
+    // forward recursion of the time kernel
+    const R* Sa = reinterpret_cast<const R*>(ad.Sa) + (size_t)g * JB * MM * 6 * NSLOT;
+    R Cl0[MM];
 #pragma unroll
-          for (int l = 0; l < MM; ++l)
+    for (int l = 0; l < MM; ++l) {
+      Cl0[l] = R(0);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) la_at(jb, l, c) = xa[jw][l][c] + xd[jw][l][c];
+      for (int d = O - 1; d >= 0; --d) Cl0[l] = R(a.tc[cl][d]) - om[l] * Cl0[l];
+    }
+#pragma unroll
+    for (int jw = 0; jw < JW; ++jw) {
+      const int lb = q + LPE * jw, jb = jb0 + jw;
+      if (lb < nb) {
+        R xl[6 * MM], h[O][6], ep[O - 1][6], dm[MM][6];
+        ldA(SC::LA + jw * SC::CA, xl);
+#pragma unroll
+        for (int k = 0; k < O; ++k) ld6(SC::HS + (k * JW + jw) * SC::C6, h[k]);
+#pragma unroll
+        for (int k = 0; k < O - 1; ++k) ld6(SC::EP + (k * JW + jw) * SC::C6, ep[k]);
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) dm[l][c] = at(Sa, ((jb * MM + l) * 6 + c) * NSLOT + slot);
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            R v = -om[l] * Cl0[l] * xl[l * 6 + c];
+            R pw = R(1);
+#pragma unroll
+            for (int k = 0; k < O; ++k) {
+              const R ht = h[k][0] + h[k][1] + h[k][2];
+              v -= pw * (bl[l] * h[k][c] + (c < 3 ? al[l] * ht : R(0)));
+              pw *= -om[l];
+            }
+            la_at(jb, l, c) = xl[l * 6 + c] + v;
+          }
+#pragma unroll
+        for (int d = 0; d < O; ++d) {
+          const R cqt = h[d][0] + h[d][1] + h[d][2];
+#pragma unroll
+          for (int l = 0; l < MM; ++l) {
+            const R tr = dm[l][0] + dm[l][1] + dm[l][2];
+            gab[2 * l] -= (double)(cqt * tr);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) gab[2 * l + 1] -= (double)(h[d][c] * dm[l][c]);
+          }
+          if (d + 1 < O)
+#pragma unroll
+            for (int l = 0; l < MM; ++l)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) dm[l][c] = om[l] * (ep[d][c] - dm[l][c]);
+        }
       }
+    }
+  }
+  if (M > 0) {
+    // the two waves add their words one after the other (LDS atomics of both
+    // at once would sum in a timing-dependent order: results would not
+    // repeat bit for bit)
+    if (w == 0 && valid)
+#pragma unroll
+      for (int k = 0; k < 2 * MM; ++k) gadd(gs, 5 + k, gab[k]);
+    __syncthreads();
+    if (w == 1 && valid)
+#pragma unroll
+      for (int k = 0; k < 2 * MM; ++k) gadd(gs, 5 + k, gab[k]);
   }
   __syncthreads();
   // the element's gradient words, split between the two waves, loads first

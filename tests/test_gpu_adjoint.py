@@ -396,11 +396,13 @@ def test_oversized_checkpoint_interval_is_refused():
 
 def test_device_pointer_boundary_matches_host():
     """The device-pointer forms of edg_upload_materials, edg_read_receivers
-    and edg_adjoint (on_device = 1) give bit for bit what the host forms give:
-    the material tables built on the device equal the host's, the
-    seismograms are the same words, and so are the gradients and the
-    initial-state adjoint (staged through the host).  A material out of range
-    in device memory is refused and changes nothing."""
+    and edg_adjoint (on_device = 1) give what the host forms give: the
+    material tables built on the device equal the host's, the seismograms
+    and the initial-state adjoint (staged through the host) are the same
+    words, and the gradients agree to rounding (the transposed prediction
+    sums an element's gradient words with LDS atomics from both of its
+    waves, in a timing-dependent order).  A material out of range in device
+    memory is refused and changes nothing."""
     import torch
     from paper_2202_10313_amd import EdgError
     out = []
@@ -433,8 +435,7 @@ def test_device_pointer_boundary_matches_host():
                                      torch.tensor(attn["yp"], device="cuda"), torch.tensor(attn["ys"], device="cuda"))
             assert e.value.code == -1
             res2 = ctx.adjoint(dj_dseis=sb, dj_dq=y)          # checkpoints and tables kept
-            for k in ("g_rho", "g_vp", "g_vs", "q0_b"):
-                assert np.array_equal(res2[k], res[k]), k
+            _assert_same_adjoint(res2, res)
         else:
             seis = ctx.read_receivers()
             res = ctx.adjoint(dj_dseis=sb, dj_dq=y)
@@ -442,8 +443,15 @@ def test_device_pointer_boundary_matches_host():
         ctx.close()
     (s0, r0), (s1, r1) = out
     assert np.array_equal(s0, s1)
-    for k in ("g_rho", "g_vp", "g_vs", "q0_b"):
-        assert np.array_equal(r0[k], r1[k]), k
+    _assert_same_adjoint(r0, r1)
+
+
+def _assert_same_adjoint(a, b):
+    assert np.array_equal(a["q0_b"], b["q0_b"])
+    for k in ("g_rho", "g_vp", "g_vs"):
+        e = np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])
+        print(f"[adjoint] repeated sweep {k}: {e:.2e}", flush=True)
+        assert e <= 1e-12, k
 
 
 def test_autograd_stale_backward_raises():
