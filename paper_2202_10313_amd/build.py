@@ -79,7 +79,8 @@ def sanitizer_runtime() -> str:
 
 def build_sanitized_host() -> dict:
     import hashlib
-    if not os.path.exists(LIB):
+    hip_names = ("kernels.o", "adjoint.o", "debug.o", "materials.o", "noalloc.o")
+    if not (os.path.exists(LIB) and all(os.path.exists(os.path.join(BUILD, o)) for o in hip_names)):
         build()
     san = os.path.join(BUILD, "san")
     os.makedirs(san, exist_ok=True)
@@ -90,7 +91,7 @@ def build_sanitized_host() -> dict:
                 h.update(name.encode() + f.read())
     with open(os.path.join(INCLUDE, "edge_lts.h"), "rb") as f:
         h.update(f.read())
-    for obj in ("kernels.o", "adjoint.o", "debug.o", "materials.o", "noalloc.o"):
+    for obj in hip_names:
         with open(os.path.join(BUILD, obj), "rb") as f:
             h.update(f.read())
     key = h.hexdigest()[:16]
@@ -109,7 +110,7 @@ def build_sanitized_host() -> dict:
 
         with ThreadPoolExecutor(max_workers=2) as ex:
             objs = list(ex.map(unit, ["host.cpp", "basis.cpp"]))
-        hip_objs = [os.path.join(BUILD, o) for o in ("kernels.o", "adjoint.o", "debug.o", "materials.o", "noalloc.o")]
+        hip_objs = [os.path.join(BUILD, o) for o in hip_names]
         _run(["g++", "-shared"] + SANITIZE + ["-o", lib + ".tmp"] + objs + hip_objs +
              ["-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
         os.replace(gen + ".tmp", gen)
