@@ -107,7 +107,8 @@ struct edg_ctx {
   // checkpoints of the forward state (adjoint): every ckpt_every cycles an
   // advance starts a segment and stores the state at its start
   int ckpt_every = 0;
-  std::vector<std::pair<int64_t, DevBuf>> ckpts;    // (level, Qe then Qa of run 0)
+  std::vector<std::pair<int64_t, DevBuf>> ckpts;    // (level, Qe then Qa of every run)
+  std::vector<DevBuf> ckpt_pool;     // buffers of dropped checkpoints, reused by the next ones
   // ahist holds, for the segment that starts at level hist_L0 and spans
   // hist_J levels, the state at the start of every level's predictions (the
   // final segment of a checkpointed advance records it; a replay rewrites it)
@@ -158,7 +159,9 @@ void dev_free(DevBuf& b) {
 }
 
 void drop_checkpoints(edg_ctx* c) {
-  for (auto& ck : c->ckpts) dev_free(ck.second);
+  // the buffers stay allocated for the next checkpoints (a hipMalloc of a
+  // whole state per segment would otherwise sit inside every forward)
+  for (auto& ck : c->ckpts) c->ckpt_pool.push_back(ck.second);
   c->ckpts.clear();
   c->hist_valid = false;
 }
@@ -845,6 +848,7 @@ edg_ctx::~edg_ctx() {
                     &agacc, &arecDb, &aseis, &ahist, &afinal, &amat, &agrad, &dmat, &dflag, &d_i2u, &d_nbr, &dbg})
     dev_free(*b);
   for (auto& ck : ckpts) dev_free(ck.second);
+  for (auto& b : ckpt_pool) dev_free(b);
   for (auto& e : ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -1170,6 +1174,9 @@ int edg_upload_clusters(edg_ctx* c, const int32_t* cluster) {
   c->run_t2 = 2 * (size_t)c->N2 * ts;
   c->run_t3 = 2 * (size_t)c->N3 * ts;
   const size_t R_ = (size_t)c->runs;
+  drop_checkpoints(c);
+  for (auto& b : c->ckpt_pool) dev_free(b);   // sized for the previous layout
+  c->ckpt_pool.clear();
   if ((rc = dev_alloc(c, c->Qe, R_ * c->run_qe * rs))) return rc;
   if ((rc = dev_alloc(c, c->Qa, std::max<size_t>(R_ * c->run_qa, 1) * rs))) return rc;
   if ((rc = dev_alloc(c, c->T1, R_ * c->run_t1 * rs))) return rc;
@@ -1519,8 +1526,21 @@ int advance_cycles(edg_ctx* c, int64_t nc, char* traces = nullptr) {
 int store_checkpoint(edg_ctx* c) {
   const size_t rs = c->cfg.fp64 ? sizeof(double) : sizeof(float);
   const size_t we = c->runs * c->run_qe, wa = c->runs * c->run_qa;
+  const size_t need = (we + wa) * rs;
   c->ckpts.emplace_back(c->level, DevBuf{});
-  int rc = dev_alloc(c, c->ckpts.back().second, (we + wa) * rs);
+  int rc = 0;
+  auto it = std::find_if(c->ckpt_pool.begin(), c->ckpt_pool.end(), [&](const DevBuf& b) { return b.bytes >= need; });
+  if (it != c->ckpt_pool.end()) {
+    c->ckpts.back().second = *it;
+    c->ckpt_pool.erase(it);
+  } else {
+    rc = dev_alloc(c, c->ckpts.back().second, need);
+    if (rc && !c->ckpt_pool.empty()) {   // the pool's buffers are too small: give them back and retry
+      for (auto& b : c->ckpt_pool) dev_free(b);
+      c->ckpt_pool.clear();
+      rc = dev_alloc(c, c->ckpts.back().second, need);
+    }
+  }
   if (rc) {
     c->ckpts.pop_back();
     return rc;
