@@ -272,7 +272,8 @@ int edg_autotune(edg_ctx* ctx, int32_t cycles, edg_plan* best, double* ms_per_cy
 /* every_cycles > 0: from now on edg_advance_to splits its cycles into
  * segments of at most every_cycles cycles and stores the state (device
  * memory, n_runs x K x Nq x B words each) at the start of every segment; 0
- * turns it off.  With one run the final segment of each edg_advance_to call
+ * turns it off.  The buffers of dropped checkpoints stay allocated for the
+ * next ones until edg_upload_clusters or edg_destroy.  With one run the final segment of each edg_advance_to call
  * also records, at every level, the state of the elements that start a step
  * there (device memory, reused by edg_adjoint; the forward kernels write
  * it; with several runs the reverse sweep replays that segment too): per LTS cycle
